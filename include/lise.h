@@ -1,0 +1,212 @@
+/*
+ * lise.h - C-ABI of the MI355X (gfx950) TDSLDA time-step library.
+ *
+ * The library evolves a set of quasiparticle wavefunctions (qpwfs) on a
+ * periodic 3D lattice under the time-dependent superfluid local density
+ * approximation of arXiv:2009.00745 (Sec. "Time-dependent superfluid local
+ * density approximation", Eq. tdslda), with the kinetic operator taken by FFT
+ * (Sec. "Discretization"), the local mean field U and pairing field Delta
+ * rebuilt from the densities of Eq. (rho_t, nu_t) and Eq. (pairingfield), and
+ * the Adams-Bashforth-Milne predictor-modifier-corrector of Sec. "Time
+ * evolution", Eq. (p), (m), (c), (y), started by the series-expansion
+ * predictor-corrector of the same section.
+ *
+ * Conventions
+ *   - hbar = m = 1.  Lattice spacing a on all three axes; x is the fastest
+ *     index.  Lattice points N = nx*ny*nz.  Qpwf j, component c, point
+ *     (z, y, x) lives at element ((j*C + c)*nz + z)*ny*nx + y*nx + x.
+ *   - C = 2 components are (u, v) = the (u_up, v_dn) block of Eq. tdslda;
+ *     C = 4 components are (u_up, u_dn, v_up, v_dn).
+ *   - Host-side qpwf and field data are complex128 (interleaved re, im) or
+ *     float64, whatever the internal precision; the library converts.
+ *   - Every call enqueues its work on the context's HIP stream (the stream
+ *     given to lise_init / lise_set_stream, e.g. PyTorch's current stream).
+ *     Calls that return host data synchronise that stream before returning.
+ *   - The context owns every device buffer it allocates; pointers passed by
+ *     the caller are borrowed for the duration of the call only.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Return value: LISE_OK (0) or a negative LISE_E_* code.  The message of
+ *     the last error is available from lise_last_error(ctx).  No exception
+ *     crosses the ABI.
+ */
+#ifndef LISE_H
+#define LISE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LISE_OK 0
+#define LISE_E_ARG (-1)          /* invalid argument (null pointer, range, size) */
+#define LISE_E_NOMEM (-2)        /* device or host allocation failed */
+#define LISE_E_UNSUPPORTED (-3)  /* lattice/precision not supported (e.g. a prime factor > 5) */
+#define LISE_E_HIP (-4)          /* a HIP runtime call or kernel launch failed */
+#define LISE_E_STATE (-5)        /* call out of order (e.g. stepping before qpwfs are set) */
+#define LISE_E_NAN (-6)          /* non-finite value detected in the densities */
+
+typedef struct lise_ctx lise_ctx;
+
+/* Periodic lattice of nx*ny*nz points with spacing a (Sec. Discretization:
+ * x_n = n a, n = 0..N-1; momenta k_n = 2 pi n / L for n < N/2 and
+ * 2 pi (n - N) / L otherwise, L = N a).  Each of nx, ny, nz must factor into
+ * 2, 3 and 5 only and lie in [1, 128]. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;
+    double a;
+} lise_lattice;
+
+/* Arithmetic of the state, FFTs and integrator.  Densities, potentials,
+ * norms and energies are always accumulated in float64. */
+typedef enum {
+    LISE_FP64 = 0,      /* complex128 state */
+    LISE_FP32 = 1,      /* complex64 state, float64 sums */
+} lise_precision;
+
+/* Functional and Hamiltonian parameters.
+ *   U(r)     = beta * n(r)^(2/3)   (self-consistent mean field)
+ *   Delta(r) = -g * kappa(r)       (Eq. pairingfield)
+ *   V(r, t)  = U(r) + U_ext(r, t), h = T + V (T = -Laplacian/2 by FFT)
+ *   U_ext    = ext_A * ramp(t) * exp(-d^2 / (2 ext_w^2)), d = minimum-image
+ *              distance to ext_r0 (Sec. "External boosts and external
+ *              potentials"); ramp = sin^2(pi t / (2 ext_t_on)) for
+ *              0 <= t < ext_t_on, else 1.
+ * C = 2 densities: n = w sum_j |v_j|^2, kappa = (w/2) sum_j v_j^* u_j.
+ * C = 4 densities (Eq. rho_t, nu_t, singlet average):
+ *   n = sum_j (|v_up|^2 + |v_dn|^2), kappa = 1/2 sum_j (v_dn^* u_up - v_up^* u_dn).
+ * frozen = 1 replaces U and Delta by the constants U0 and Delta0 (test mode).
+ * C = 2 uses mu_up as its single chemical potential. */
+typedef struct {
+    int32_t ncomp;          /* 2 or 4 */
+    int32_t precision;      /* lise_precision */
+    double mu_up, mu_dn;
+    double beta, g, w;
+    int32_t frozen;
+    int32_t reserved;
+    double U0, Delta0_re, Delta0_im;
+    double ext_A, ext_w;
+    double ext_r0[3];
+    double ext_t_on;
+} lise_functional;
+
+/* Observables of the current state (Sec. "Miscellaneous quantities" and the
+ * cold-atom energy):
+ *   N = a^3 sum_r n;  E = E_kin + E_int + E_pair + E_ext with
+ *   E_kin  = a^3 sum_r weight * sum_j Re(v_j^* T v_j)  (same T as the step),
+ *   E_int  = a^3 sum_r (3/5) beta n^(5/3),  E_pair = a^3 sum_r g |kappa|^2,
+ *   E_ext  = a^3 sum_r U_ext n;
+ *   mean_abs_delta = sum |Delta| n / sum n;  r_cm = sum r n / sum n;
+ *   norm_drift_* = max / mean over j of |<psi_j|psi_j> - <psi_j|psi_j>_0|,
+ *   relative to the norms when the qpwfs were last set. */
+typedef struct {
+    double t;
+    int64_t step;
+    double N, E, E_kin, E_int, E_pair, E_ext;
+    double mean_abs_delta;
+    double r_cm[3];
+    double norm_drift_max, norm_drift_mean;
+} lise_obs;
+
+/* Launch tuning (0 = library default).
+ *   chunk_qpwf : qpwfs per launch of the two apply-H kernels (bounds the
+ *                scratch buffer and keeps it cache-resident)
+ *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
+ *                (sets the number of density partial sums)
+ *   fused      : 0 or 1 = whole-cube kernel when the cube fits in LDS,
+ *                -1 = never (always the z-axis kernel plus plane kernel) */
+typedef struct {
+    int32_t chunk_qpwf;
+    int32_t jgroup;
+    int32_t fused;
+    int32_t reserved;
+} lise_tuning;
+
+/* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the
+ * HIP stream `hip_stream` (hipStream_t; NULL = the null stream).  Allocates
+ * the seven state copies of the ABM history (y_n, y_{n-1}, four derivative
+ * levels, p - c) plus scratch.  The qpwfs are undefined until lise_set_qpwf
+ * has covered all of them.  Errors: ARG, UNSUPPORTED, NOMEM, HIP. */
+int lise_init(lise_ctx **out, const lise_lattice *lat, int64_t n_qpwf,
+              const lise_functional *fn, void *hip_stream);
+
+/* Copy qpwfs [first, first+count) from `src` (complex128, count*C*N
+ * elements, layout above) into the state; `src_is_device` = 1 when src is a
+ * device pointer.  Resets the time to t = 0 (or keeps t if already set, see
+ * lise_set_time), discards the ABM history, and marks densities stale.
+ * Errors: ARG, STATE, HIP. */
+int lise_set_qpwf(lise_ctx *c, int64_t first, int64_t count, const void *src, int32_t src_is_device);
+
+/* Copy qpwfs [first, first+count) of the current state y_n to `dst`
+ * (complex128).  Errors: ARG, HIP. */
+int lise_get_qpwf(lise_ctx *c, int64_t first, int64_t count, void *dst, int32_t dst_is_device);
+
+/* H psi (Eq. tdslda, with h = T + V, h_updn = 0) for qpwfs [first,
+ * first+count) of the current state, with U and Delta built from the
+ * densities of the whole current state at the current time.  `out` receives
+ * count*C*N complex128 values (device pointer if out_is_device = 1, else
+ * host).  Errors: ARG, STATE, HIP. */
+int lise_apply_h(lise_ctx *c, int64_t first, int64_t count, void *out, int32_t out_is_device);
+
+/* Series-expansion start-up (Sec. "Time evolution"): three predictor-
+ * corrector steps of order 4 with corrector densities (n_pre + n)/2 taken at
+ * t + dt/2; stores y'_0, y'_1, y'_2 = -i H y_s, y_2, y_3 and p_3 - c_3 = 0.
+ * Advances t by 3 dt.  Errors: STATE, HIP, NAN. */
+int lise_startup(lise_ctx *c, double dt);
+
+/* Advance `nsteps` ABM steps (Eq. p, m, c, y; predictor coefficient of
+ * y'_n = 119).  Runs lise_startup first when there is no history or when dt
+ * differs from the history's step.  Per step: apply H to y_n, form p and m,
+ * rebuild n, kappa, U, Delta from m at t + dt, apply H to m, form c and
+ * y_{n+1}, rebuild the fields from y_{n+1}.  Errors: STATE, HIP, NAN. */
+int lise_step(lise_ctx *c, double dt, int64_t nsteps);
+
+/* Densities of the current state: n (N float64) and kappa (N complex128,
+ * interleaved).  Either pointer may be NULL.  Errors: ARG, STATE, HIP. */
+int lise_densities(lise_ctx *c, double *n_out, double *kappa_out, int32_t out_is_device);
+
+/* Observables of the current state (see lise_obs).  Errors: ARG, STATE, HIP. */
+int lise_observables(lise_ctx *c, lise_obs *out);
+
+/* Current time and number of steps taken (start-up steps count). */
+int lise_get_time(const lise_ctx *c, double *t, int64_t *step);
+
+/* Set the time of the current state (before stepping). Errors: ARG. */
+int lise_set_time(lise_ctx *c, double t);
+
+/* Replace the stream all later work is enqueued on. */
+int lise_set_stream(lise_ctx *c, void *hip_stream);
+
+/* Override launch tuning (see lise_tuning).  Reallocates scratch as needed.
+ * Errors: ARG, NOMEM. */
+int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * lise_profile(c, 1) starts recording an event pair around every launch of
+ * the library's kernels; lise_profile(c, 0) stops.  lise_profile_read
+ * synchronises, then returns for kernel class `which` (0 = plane kernel of
+ * the ABM phases, 1 = z-axis kernel, 2 = density reduction + potentials,
+ * 3 = plane kernel outside the ABM phases: start-up, apply-H, energy) the
+ * number of launches and their summed duration in milliseconds, and clears
+ * the counters of every class. */
+int lise_profile(lise_ctx *c, int32_t enable);
+int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
+
+/* Bytes of device memory the context holds. */
+int lise_memory(const lise_ctx *c, int64_t *bytes);
+
+/* Text of the last error on this context (never NULL). */
+const char *lise_last_error(const lise_ctx *c);
+
+/* Library version string. */
+const char *lise_version(void);
+
+/* Release every device buffer and the context.  NULL is a no-op. */
+void lise_free(lise_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LISE_H */

@@ -1,0 +1,994 @@
+// Host side of the MI355X TDSLDA step library: context, device buffers, FFT
+// plans, the series-expansion start-up and the two-phase ABM schedule, and
+// the C-ABI declared in include/lise.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lise.h"
+#include "lise_device.hpp"
+
+using namespace lise;
+
+namespace {
+
+constexpr int kThreads = 256;
+const char* kVersion = "lise-mi355x 0.1 (gfx950)";
+
+// ---------------------------------------------------------------------------
+// FFT plans
+
+bool factorize(int n, int* radix, int* nst) {
+    if (n < 1) return false;
+    int e2 = 0, m = n;
+    while (m % 2 == 0) { m /= 2; ++e2; }
+    std::vector<int> r;
+    // powers of two: prefer radix 8, then a 4-4 or 4 or 2 remainder
+    int rem = e2;
+    while (rem >= 3 && !(rem == 4)) { r.push_back(8); rem -= 3; }
+    if (rem == 4) { r.push_back(4); r.push_back(4); rem = 0; }
+    if (rem == 2) { r.push_back(4); rem = 0; }
+    if (rem == 1) { r.push_back(2); rem = 0; }
+    while (m % 3 == 0) { r.push_back(3); m /= 3; }
+    while (m % 5 == 0) { r.push_back(5); m /= 5; }
+    if (m != 1) return false;
+    if ((int)r.size() > kMaxStages) return false;
+    *nst = (int)r.size();
+    for (size_t i = 0; i < r.size(); ++i) radix[i] = r[i];
+    return true;
+}
+
+// Build the plan of one axis and append its twiddles (double precision,
+// angles reduced exactly: 2 pi (q k mod (pR)) / (pR)).
+bool make_plan(int n, AxisPlan* pl, std::vector<cpx<double>>* tw) {
+    std::memset(pl, 0, sizeof(*pl));
+    pl->n = n;
+    if (!factorize(n, pl->radix, &pl->nst)) return false;
+    int p = 1;
+    for (int s = 0; s < pl->nst; ++s) {
+        const int R = pl->radix[s];
+        pl->p[s] = p;
+        pl->tw[s] = (int)tw->size();
+        const long long pr = (long long)p * R;
+        for (int k = 0; k < p; ++k)
+            for (int q = 1; q < R; ++q) {
+                const long long num = ((long long)q * k) % pr;
+                const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)num / (long double)pr;
+                cpx<double> w;
+                w.re = (double)cosl(ang);
+                w.im = (double)sinl(ang);
+                tw->push_back(w);
+            }
+        p *= R;
+    }
+    return true;
+}
+
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    double total_ms[4] = {0, 0, 0, 0};
+    long long count[4] = {0, 0, 0, 0};
+};
+
+}  // namespace
+
+struct lise_ctx {
+    lise_lattice lat;
+    lise_functional fn;
+    long long M = 0, N = 0;
+    int C = 2;
+    int prec = LISE_FP64;
+    size_t esz = 16;          // bytes per complex element of the state
+    long long per = 0;        // elements per qpwf = C * N
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t lds_limit = 65536;
+
+    void* buf[7] = {nullptr};  // 0,1: y ring; 2..5: derivative ring; 6: p - c
+    void* G = nullptr;         // z-axis scratch, chunk qpwfs
+    long long g_cap = 0;       // qpwfs G holds
+    double* dpart = nullptr;   // density partial slots
+    int slot_cap = 0;
+    double* dens_cur = nullptr;
+    double* dens_tmp = nullptr;
+    double* V_cur = nullptr;
+    double* D_cur = nullptr;
+    double* V_tmp = nullptr;
+    double* D_tmp = nullptr;
+    void* tw = nullptr;
+    double* red = nullptr;     // reduction partials (observables)
+    long long red_cap = 0;
+    double* norms = nullptr;
+    double* norms0 = nullptr;
+    int* bad = nullptr;
+    AxisPlan px, py, pz;
+
+    // tuning
+    int chunk = 0, jg = 16, fused_pref = 1;
+    bool fused = false;
+    int zb = 1, yb = 1, ppt = 4;
+
+    // state
+    std::vector<char> set_mask;   // which qpwfs were set (coarse: count)
+    long long n_set = 0;
+    bool dens_valid = false;
+    bool hist = false;
+    bool norms0_valid = false;
+    double dt_hist = 0.0;
+    double t = 0.0;
+    long long step = 0;
+    int iy = 0;   // buf index of y_n (0 or 1)
+    int dn = 0;   // derivative slot receiving y'_n (0..3)
+
+    Prof prof;
+    char err[512] = {0};
+};
+
+namespace {
+
+int fail(lise_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(ctx, LISE_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(call)                  \
+    do {                           \
+        int rc_ = (call);          \
+        if (rc_ != LISE_OK) return rc_; \
+    } while (0)
+
+template <typename T>
+cpx<T>* S(lise_ctx* c, int i) { return reinterpret_cast<cpx<T>*>(c->buf[i]); }
+
+// ---- profiling -------------------------------------------------------------
+void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!c->prof.on || c->prof.used + 2 > c->prof.pool.size()) return;
+    *ev = c->prof.pool[c->prof.used];
+    (void)hipEventRecord(*ev, c->stream);
+    (void)cls;
+}
+void prof_end(lise_ctx* c, int cls, hipEvent_t a) {
+    if (!a) return;
+    hipEvent_t b = c->prof.pool[c->prof.used + 1];
+    c->prof.used += 2;
+    (void)hipEventRecord(b, c->stream);
+    c->prof.recs.push_back({cls, a, b});
+}
+
+int check_launch(lise_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LISE_E_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return LISE_OK;
+}
+
+// ---- allocation -------------------------------------------------------------
+int dalloc(lise_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, LISE_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return LISE_OK;
+}
+
+void dfree(void** p) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+size_t kp_lds_bytes(const lise_ctx* c, int zb) { return 2ull * 2ull * (size_t)zb * c->lat.nx * c->lat.ny * c->esz; }
+size_t kz_lds_bytes(const lise_ctx* c, int yb) { return 2ull * (size_t)c->lat.nz * yb * c->lat.nx * c->esz; }
+
+// Choose launch geometry and (re)allocate scratch for the current tuning.
+int configure(lise_ctx* c) {
+    const int nx = c->lat.nx, ny = c->lat.ny, nz = c->lat.nz;
+    const long long nxy = (long long)nx * ny;
+    // fused: the whole cube of one component pair in LDS (two buffers)
+    c->fused = false;
+    if (c->fused_pref && kp_lds_bytes(c, nz) <= c->lds_limit && c->N <= 16LL * kThreads) c->fused = true;
+    if (c->fused) {
+        c->zb = nz;
+    } else {
+        int zb = 1;
+        for (int d = 1; d <= nz; ++d)
+            if (nz % d == 0 && d * nxy >= kThreads && kp_lds_bytes(c, d) <= c->lds_limit) { zb = d; break; }
+        c->zb = zb;
+        if (kp_lds_bytes(c, zb) > c->lds_limit)
+            return fail(c, LISE_E_UNSUPPORTED, "xy-plane %dx%d does not fit in LDS (%zu > %zu bytes)", nx, ny,
+                        kp_lds_bytes(c, zb), c->lds_limit);
+        int yb = 1;
+        for (int d = ny; d >= 1; --d)
+            if (ny % d == 0 && (long long)d * nx * nz <= (c->prec == LISE_FP64 ? 2048 : 4096) &&
+                kz_lds_bytes(c, d) <= c->lds_limit) { yb = d; break; }
+        c->yb = yb;
+        if (kz_lds_bytes(c, yb) > c->lds_limit)
+            return fail(c, LISE_E_UNSUPPORTED, "xz-tile does not fit in LDS");
+    }
+    const long long P = (long long)c->zb * nxy;
+    const long long ppt = (P + kThreads - 1) / kThreads;
+    if (ppt > 16) return fail(c, LISE_E_UNSUPPORTED, "plane stack of %lld points exceeds 16 per thread", P);
+    c->ppt = ppt <= 4 ? 4 : 16;
+
+    long long chunk = c->chunk > 0 ? c->chunk : 0;
+    if (chunk <= 0) {
+        // default: a z-scratch of ~256 MB (the size of the Infinity Cache)
+        const long long per_bytes = c->per * (long long)c->esz;
+        chunk = std::max<long long>(c->jg, (256LL << 20) / std::max<long long>(per_bytes, 1));
+    }
+    chunk = std::min<long long>(chunk, c->M);
+    chunk = std::max<long long>(chunk, 1);
+    c->chunk = (int)chunk;
+    const int slots = (int)((chunk + c->jg - 1) / c->jg);
+    const long long dens_slots = std::max<long long>(slots, (c->M + c->jg - 1) / c->jg);
+    if (!c->fused && c->g_cap < chunk) {
+        dfree(&c->G);
+        CHK(dalloc(c, &c->G, (size_t)chunk * c->per * c->esz));
+        c->g_cap = chunk;
+    }
+    if (c->slot_cap < dens_slots) {
+        dfree(reinterpret_cast<void**>(&c->dpart));
+        CHK(dalloc(c, reinterpret_cast<void**>(&c->dpart), (size_t)dens_slots * 3 * c->N * sizeof(double)));
+        c->slot_cap = (int)dens_slots;
+    }
+    return LISE_OK;
+}
+
+FieldParams field_params(const lise_ctx* c) {
+    FieldParams f;
+    f.nx = c->lat.nx;
+    f.ny = c->lat.ny;
+    f.nz = c->lat.nz;
+    f.a = c->lat.a;
+    f.beta = c->fn.beta;
+    f.g = c->fn.g;
+    f.frozen = c->fn.frozen;
+    f.U0 = c->fn.U0;
+    f.D0re = c->fn.Delta0_re;
+    f.D0im = c->fn.Delta0_im;
+    f.extA = c->fn.ext_A;
+    f.extw = c->fn.ext_w;
+    f.r0x = c->fn.ext_r0[0];
+    f.r0y = c->fn.ext_r0[1];
+    f.r0z = c->fn.ext_r0[2];
+    f.t_on = c->fn.ext_t_on;
+    return f;
+}
+
+// ---- kernel launchers ---------------------------------------------------------
+
+template <typename T>
+KPArgs<T> kp_base(lise_ctx* c) {
+    KPArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = c->lat.nx;
+    a.ny = c->lat.ny;
+    a.nz = c->lat.nz;
+    a.C = c->C;
+    a.npair = c->C / 2;
+    a.zb = c->zb;
+    a.jg = c->jg;
+    a.fused = c->fused ? 1 : 0;
+    a.px = c->px;
+    a.py = c->py;
+    a.pz = c->pz;
+    a.tw = reinterpret_cast<const cpx<T>*>(c->tw);
+    const double pi = 3.14159265358979323846;
+    const double tsize = c->fused ? (double)c->N : (double)c->lat.nx * c->lat.ny;
+    const double lx = c->lat.nx * c->lat.a, ly = c->lat.ny * c->lat.a, lz = c->lat.nz * c->lat.a;
+    a.cx = T(2.0 * pi * pi / (lx * lx) / tsize);
+    a.cy = T(2.0 * pi * pi / (ly * ly) / tsize);
+    a.cz = T(2.0 * pi * pi / (lz * lz) / tsize);
+    if (c->C == 2) {
+        a.ca[0] = 0; a.cb[0] = 1; a.sgn[0] = 1;
+        a.mu_a[0] = a.mu_b[0] = c->fn.mu_up;
+        a.w = c->fn.w;
+    } else {
+        a.ca[0] = 0; a.cb[0] = 3; a.sgn[0] = 1; a.mu_a[0] = c->fn.mu_up; a.mu_b[0] = c->fn.mu_dn;
+        a.ca[1] = 1; a.cb[1] = 2; a.sgn[1] = -1; a.mu_a[1] = c->fn.mu_dn; a.mu_b[1] = c->fn.mu_up;
+        a.w = 1.0;
+    }
+    a.dpart = c->dpart;
+    return a;
+}
+
+template <typename T, int MODE>
+int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
+    a.j0 = j0;
+    a.kcount = k;
+    dim3 grid(c->lat.nz / c->zb, (k + c->jg - 1) / c->jg);
+    // the kinetic-energy mode reuses LDS for a 256-double reduction
+    const size_t lds = std::max(kp_lds_bytes(c, c->zb), (size_t)kThreads * sizeof(double));
+    hipEvent_t ev;
+    prof_begin(c, cls, &ev);
+    if (c->ppt == 4) {
+        if (lds > 65536) (void)hipFuncSetAttribute((const void*)kp_kernel<T, MODE, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((kp_kernel<T, MODE, 4>), grid, dim3(kThreads), lds, c->stream, a);
+    } else {
+        if (lds > 65536) (void)hipFuncSetAttribute((const void*)kp_kernel<T, MODE, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((kp_kernel<T, MODE, 16>), grid, dim3(kThreads), lds, c->stream, a);
+    }
+    prof_end(c, cls, ev);
+    return check_launch(c, "kp_kernel");
+}
+
+template <typename T>
+int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k) {
+    KZArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = c->lat.nx;
+    a.ny = c->lat.ny;
+    a.nz = c->lat.nz;
+    a.C = c->C;
+    a.yb = c->yb;
+    a.j0 = j0;
+    a.pz = c->pz;
+    a.tw = reinterpret_cast<const cpx<T>*>(c->tw);
+    const double pi = 3.14159265358979323846;
+    const double lz = c->lat.nz * c->lat.a;
+    a.cz = T(2.0 * pi * pi / (lz * lz) / c->lat.nz);
+    a.in = in;
+    a.G = reinterpret_cast<cpx<T>*>(c->G);
+    dim3 grid(c->lat.ny / c->yb, (unsigned)(k * c->C));
+    const size_t lds = kz_lds_bytes(c, c->yb);
+    hipEvent_t ev;
+    prof_begin(c, 1, &ev);
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kz_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((kz_kernel<T>), grid, dim3(kThreads), lds, c->stream, a);
+    prof_end(c, 1, ev);
+    return check_launch(c, "kz_kernel");
+}
+
+// One Hamiltonian application over all qpwfs [first, first+count) in chunks:
+// z-axis kernel (unless fused) then the plane kernel of the given mode.
+template <typename T, int MODE>
+int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int cls) {
+    const int dens = a.dens_src;
+    for (long long j0 = first, ci = 0; j0 < first + count; j0 += c->chunk, ++ci) {
+        const int k = (int)std::min<long long>(c->chunk, first + count - j0);
+        if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k));
+        a.accumulate = (dens && ci > 0) ? 1 : 0;
+        CHK((launch_kp_t<T, MODE>(c, a, j0, k, cls)));
+    }
+    return LISE_OK;
+}
+
+int slots_used(const lise_ctx* c, long long count) {
+    const long long k = std::min<long long>(c->chunk, count);
+    return (int)((k + c->jg - 1) / c->jg);
+}
+
+// Reduce density partials (nslots > 0) or reuse dens (nslots = 0), optional
+// average, then fields at time t.
+int launch_fields(lise_ctx* c, int nslots, const double* avg_with, double* dens, double* V, double* D, double t) {
+    dim3 grid((unsigned)((c->N + kThreads - 1) / kThreads));
+    hipEvent_t ev;
+    prof_begin(c, 2, &ev);
+    hipLaunchKernelGGL(fields_kernel, grid, dim3(kThreads), 0, c->stream, c->dpart, nslots, c->N, avg_with, dens, V,
+                       D, field_params(c), t, c->bad);
+    prof_end(c, 2, ev);
+    return check_launch(c, "fields_kernel");
+}
+
+template <typename T>
+int dens_direct_t(lise_ctx* c, const cpx<T>* state) {
+    const long long slots = (c->M + c->jg - 1) / c->jg;
+    dim3 grid((unsigned)((c->N + kThreads - 1) / kThreads), (unsigned)slots);
+    hipLaunchKernelGGL((dens_partial_kernel<T>), grid, dim3(kThreads), 0, c->stream, state, c->C, c->N, c->M, c->jg,
+                       c->C == 2 ? c->fn.w : 1.0, c->dpart);
+    CHK(check_launch(c, "dens_partial_kernel"));
+    return launch_fields(c, (int)slots, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t);
+}
+
+int check_bad(lise_ctx* c) {
+    int h = 0;
+    HIPCHK(c, hipMemcpyAsync(&h, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h) {
+        HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+        return fail(c, LISE_E_NAN, "non-finite density encountered at t = %g", c->t);
+    }
+    return LISE_OK;
+}
+
+template <typename T>
+cpx<T>* ycur(lise_ctx* c) { return S<T>(c, c->iy); }
+
+template <typename T>
+int ensure_fields_t(lise_ctx* c) {
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set (%lld of %lld)", c->n_set, c->M);
+    if (!c->dens_valid) {
+        CHK(dens_direct_t<T>(c, ycur<T>(c)));
+        c->dens_valid = true;
+    }
+    return LISE_OK;
+}
+
+// ---- start-up: series-expansion predictor-corrector -----------------------------
+
+// acc = sum_{q<=4} (-i dt H)^q / q! psi with the fields (V, D); term buffer
+// `term`; optional derivative output -i H psi; densities of acc into dpart.
+template <typename T>
+int taylor_t(lise_ctx* c, const cpx<T>* psi, cpx<T>* term, cpx<T>* acc, cpx<T>* deriv, const double* V,
+             const double* D, double dt) {
+    for (int q = 1; q <= 4; ++q) {
+        KPArgs<T> a = kp_base<T>(c);
+        a.V = V;
+        a.D = D;
+        a.in = (q == 1) ? psi : term;
+        a.G = reinterpret_cast<const cpx<T>*>(c->G);
+        a.out = term;
+        a.acc = acc;
+        a.acc_from_in = (q == 1);
+        a.deriv = (q == 1) ? deriv : nullptr;
+        a.coef_re = 0.0;
+        a.coef_im = -dt / q;
+        a.dens_src = (q == 4);
+        CHK((apply_chunks<T, KP_APPLY>(c, a, 0, c->M, 3)));
+    }
+    return LISE_OK;
+}
+
+template <typename T>
+int startup_t(lise_ctx* c, double dt) {
+    CHK(ensure_fields_t<T>(c));
+    // fields of y_0 at t_0
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    int ys = c->iy;             // buffer of Y_s
+    const int term = 6;         // p - c slot used as term buffer during start-up
+    for (int s = 0; s < 3; ++s) {
+        const int acc = 1 - ys;
+        // predictor with H(t_s); stores y'_s in derivative slot s
+        CHK(taylor_t<T>(c, S<T>(c, ys), S<T>(c, term), S<T>(c, acc), S<T>(c, 2 + s), c->V_cur, c->D_cur, dt));
+        // corrector fields from (n_pre + n_s)/2 at t_s + dt/2
+        CHK(launch_fields(c, slots_used(c, c->M), c->dens_cur, c->dens_tmp, c->V_tmp, c->D_tmp, c->t + 0.5 * dt));
+        CHK(taylor_t<T>(c, S<T>(c, ys), S<T>(c, term), S<T>(c, acc), nullptr, c->V_tmp, c->D_tmp, dt));
+        c->t += dt;
+        c->step += 1;
+        // densities of Y_{s+1} -> fields at t_{s+1}
+        CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+        ys = acc;
+    }
+    // y_n = Y_3 (buffer ys), y_{n-1} = Y_2; derivatives y'_0..y'_2 in slots 0..2
+    c->iy = ys;
+    c->dn = 3;
+    HIPCHK(c, hipMemsetAsync(c->buf[6], 0, (size_t)c->M * c->per * c->esz, c->stream));
+    c->hist = true;
+    c->dt_hist = dt;
+    return check_bad(c);
+}
+
+// ---- one ABM step ------------------------------------------------------------------
+
+template <typename T>
+int abm_step_t(lise_ctx* c) {
+    const double dt = c->dt_hist;
+    const int d0 = 2 + c->dn;                   // receives y'_n
+    const int d1 = 2 + (c->dn + 3) % 4;         // y'_{n-1}
+    const int d2 = 2 + (c->dn + 2) % 4;         // y'_{n-2}
+    const int d3 = 2 + (c->dn + 1) % 4;         // y'_{n-3}, then m
+    const int yn = c->iy, ym1 = 1 - c->iy;
+    // phase 1: H y_n -> y'_n, p, m; densities of m
+    {
+        KPArgs<T> a = kp_base<T>(c);
+        a.V = c->V_cur;
+        a.D = c->D_cur;
+        a.in = S<T>(c, yn);
+        a.G = reinterpret_cast<const cpx<T>*>(c->G);
+        a.a1 = S<T>(c, ym1);
+        a.a2 = S<T>(c, d1);
+        a.a3 = S<T>(c, d2);
+        a.a4 = S<T>(c, d3);
+        a.a5 = S<T>(c, 6);
+        a.a6 = S<T>(c, d0);
+        a.dt = dt;
+        a.dens_src = 1;
+        CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0)));
+    }
+    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, c->t + dt));
+    // phase 2: H m -> m', c, y_{n+1}, d_{n+1}; densities of y_{n+1}
+    {
+        KPArgs<T> a = kp_base<T>(c);
+        a.V = c->V_tmp;
+        a.D = c->D_tmp;
+        a.in = S<T>(c, d3);
+        a.G = reinterpret_cast<const cpx<T>*>(c->G);
+        a.a1 = S<T>(c, 6);
+        a.a2 = S<T>(c, yn);
+        a.a3 = S<T>(c, ym1);
+        a.a4 = S<T>(c, d0);
+        a.a5 = S<T>(c, d1);
+        a.a6 = S<T>(c, d2);
+        a.dt = dt;
+        a.dens_src = 1;
+        CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0)));
+    }
+    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t + dt));
+    c->iy = ym1;
+    c->dn = (c->dn + 1) % 4;
+    c->t += dt;
+    c->step += 1;
+    return LISE_OK;
+}
+
+template <typename T>
+int step_t(lise_ctx* c, double dt, long long nsteps) {
+    if (!c->hist || c->dt_hist != dt) CHK(startup_t<T>(c, dt));
+    for (long long s = 0; s < nsteps; ++s) CHK(abm_step_t<T>(c));
+    return check_bad(c);
+}
+
+template <typename T>
+int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_is_device) {
+    CHK(ensure_fields_t<T>(c));
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    // H psi into the p - c slot when there is no history, else a temporary
+    void* tmp = nullptr;
+    cpx<T>* dst;
+    const size_t nbytes = (size_t)count * c->per * c->esz;
+    if (c->hist) {
+        CHK(dalloc(c, &tmp, nbytes));
+        dst = reinterpret_cast<cpx<T>*>(tmp) - first * c->per;
+    } else {
+        dst = S<T>(c, 6);
+    }
+    KPArgs<T> a = kp_base<T>(c);
+    a.V = c->V_cur;
+    a.D = c->D_cur;
+    a.in = ycur<T>(c);
+    a.G = reinterpret_cast<const cpx<T>*>(c->G);
+    a.out = dst;
+    a.coef_re = 1.0;
+    a.coef_im = 0.0;
+    a.dens_src = 0;
+    int rc = apply_chunks<T, KP_APPLY>(c, a, first, count, 3);
+    if (rc == LISE_OK) {
+        const cpx<T>* src = dst + first * c->per;
+        const long long n = count * c->per;
+        void* d64 = out;
+        void* stage = nullptr;
+        if (!out_is_device) {
+            rc = dalloc(c, &stage, (size_t)n * sizeof(cpx<double>));
+            d64 = stage;
+        }
+        if (rc == LISE_OK) {
+            hipLaunchKernelGGL((convert_kernel<double, T>), dim3(2048), dim3(kThreads), 0, c->stream, src,
+                               reinterpret_cast<cpx<double>*>(d64), n);
+            rc = check_launch(c, "convert_kernel");
+        }
+        if (rc == LISE_OK && !out_is_device) {
+            hipError_t e = hipMemcpyAsync(out, stage, (size_t)n * sizeof(cpx<double>), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rc = fail(c, LISE_E_HIP, "copy of H psi failed: %s", hipGetErrorString(e));
+        }
+        if (stage) { (void)hipStreamSynchronize(c->stream); dfree(&stage); }
+    }
+    if (tmp) { (void)hipStreamSynchronize(c->stream); dfree(&tmp); }
+    return rc;
+}
+
+template <typename T>
+int kinetic_energy_t(lise_ctx* c, double* ekin) {
+    KPArgs<T> a = kp_base<T>(c);
+    a.V = c->V_cur;
+    a.D = c->D_cur;
+    a.in = ycur<T>(c);
+    a.G = reinterpret_cast<const cpx<T>*>(c->G);
+    const long long nwg_per = (long long)(c->lat.nz / c->zb) * ((c->chunk + c->jg - 1) / c->jg);
+    if (c->red_cap < nwg_per) {
+        dfree(reinterpret_cast<void**>(&c->red));
+        CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)std::max<long long>(nwg_per, 4096) * sizeof(double)));
+        c->red_cap = std::max<long long>(nwg_per, 4096);
+    }
+    a.epart = c->red;
+    std::vector<double> h(nwg_per);
+    double sum = 0.0;
+    for (long long j0 = 0; j0 < c->M; j0 += c->chunk) {
+        const int k = (int)std::min<long long>(c->chunk, c->M - j0);
+        if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k));
+        CHK((launch_kp_t<T, KP_KINETIC>(c, a, j0, k, 3)));
+        const long long nwg = (long long)(c->lat.nz / c->zb) * ((k + c->jg - 1) / c->jg);
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->red, nwg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (long long i = 0; i < nwg; ++i) sum += h[i];
+    }
+    *ekin = sum * c->lat.a * c->lat.a * c->lat.a;
+    return LISE_OK;
+}
+
+template <typename T>
+int norms_t(lise_ctx* c, double* dst) {
+    hipLaunchKernelGGL((norm_kernel<T>), dim3((unsigned)c->M), dim3(kThreads), 0, c->stream, ycur<T>(c), c->per, dst);
+    return check_launch(c, "norm_kernel");
+}
+
+template <typename T>
+int observables_t(lise_ctx* c, lise_obs* o) {
+    CHK(ensure_fields_t<T>(c));
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    const int nblk = 256;
+    if (c->red_cap < nblk * kNObs) {
+        dfree(reinterpret_cast<void**>(&c->red));
+        CHK(dalloc(c, reinterpret_cast<void**>(&c->red), 4096 * sizeof(double)));
+        c->red_cap = 4096;
+    }
+    hipLaunchKernelGGL(obs_fields_kernel, dim3(nblk), dim3(kThreads), 0, c->stream, c->dens_cur, c->D_cur, c->N,
+                       field_params(c), c->t, c->red);
+    CHK(check_launch(c, "obs_fields_kernel"));
+    std::vector<double> h(nblk * kNObs);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->red, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s[kNObs] = {0};
+    for (int b = 0; b < nblk; ++b)
+        for (int k = 0; k < kNObs; ++k) s[k] += h[b * kNObs + k];
+    double ekin = 0.0;
+    CHK(kinetic_energy_t<T>(c, &ekin));
+    const double a3 = c->lat.a * c->lat.a * c->lat.a;
+    std::memset(o, 0, sizeof(*o));
+    o->t = c->t;
+    o->step = c->step;
+    o->N = a3 * s[0];
+    o->E_kin = ekin;
+    o->E_int = a3 * s[4];
+    o->E_pair = a3 * s[5];
+    o->E_ext = a3 * s[6];
+    o->E = o->E_kin + o->E_int + o->E_pair + o->E_ext;
+    o->mean_abs_delta = s[0] != 0.0 ? s[7] / s[0] : 0.0;
+    for (int k = 0; k < 3; ++k) o->r_cm[k] = s[0] != 0.0 ? s[1 + k] / s[0] : 0.0;
+    // norm drift
+    CHK(norms_t<T>(c, c->norms));
+    std::vector<double> n1(c->M), n0(c->M);
+    HIPCHK(c, hipMemcpyAsync(n1.data(), c->norms, c->M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n0.data(), c->norms0, c->M * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double mx = 0.0, mean = 0.0;
+    for (long long j = 0; j < c->M; ++j) {
+        const double d = std::fabs(n1[j] - n0[j]) * a3;
+        mx = std::max(mx, d);
+        mean += d;
+    }
+    o->norm_drift_max = mx;
+    o->norm_drift_mean = c->M ? mean / c->M : 0.0;
+    return LISE_OK;
+}
+
+int valid_dim(int n) {
+    if (n < 1 || n > 128) return 0;
+    int m = n;
+    for (int p : {2, 3, 5})
+        while (m % p == 0) m /= p;
+    return m == 1;
+}
+
+}  // namespace
+
+// =============================================================================
+// C-ABI
+
+extern "C" {
+
+int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lise_functional* fn, void* hip_stream) {
+    if (!out || !lat || !fn) return LISE_E_ARG;
+    *out = nullptr;
+    lise_ctx* c = new (std::nothrow) lise_ctx();
+    if (!c) return LISE_E_NOMEM;
+    auto bail = [&](int rc) {
+        fprintf(stderr, "lise_init: %s\n", c->err);
+        lise_free(c);
+        return rc;
+    };
+    c->lat = *lat;
+    c->fn = *fn;
+    if (!(lat->a > 0.0)) return bail(fail(c, LISE_E_ARG, "lattice spacing must be positive"));
+    if (!valid_dim(lat->nx) || !valid_dim(lat->ny) || !valid_dim(lat->nz))
+        return bail(fail(c, LISE_E_UNSUPPORTED, "lattice %dx%dx%d: each side must be 1..128 with prime factors 2,3,5",
+                         lat->nx, lat->ny, lat->nz));
+    if (n_qpwf < 1) return bail(fail(c, LISE_E_ARG, "n_qpwf must be >= 1"));
+    if (fn->ncomp != 2 && fn->ncomp != 4) return bail(fail(c, LISE_E_ARG, "ncomp must be 2 or 4"));
+    if (fn->precision != LISE_FP64 && fn->precision != LISE_FP32)
+        return bail(fail(c, LISE_E_UNSUPPORTED, "precision %d not supported", fn->precision));
+    c->C = fn->ncomp;
+    c->prec = fn->precision;
+    c->esz = c->prec == LISE_FP64 ? 16 : 8;
+    c->M = n_qpwf;
+    c->N = (long long)lat->nx * lat->ny * lat->nz;
+    c->per = (long long)c->C * c->N;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, c->device);
+    if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e)));
+    c->lds_limit = prop.sharedMemPerBlock;
+    // plans and twiddles
+    std::vector<cpx<double>> tw;
+    if (!make_plan(lat->nx, &c->px, &tw) || !make_plan(lat->ny, &c->py, &tw) || !make_plan(lat->nz, &c->pz, &tw))
+        return bail(fail(c, LISE_E_UNSUPPORTED, "no FFT plan"));
+    if (c->prec == LISE_FP64) {
+        int rc = dalloc(c, &c->tw, tw.size() * sizeof(cpx<double>));
+        if (rc) return bail(rc);
+        e = hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(cpx<double>), hipMemcpyHostToDevice);
+    } else {
+        std::vector<cpx<float>> tf(tw.size());
+        for (size_t i = 0; i < tw.size(); ++i) {
+            tf[i].re = (float)tw[i].re;
+            tf[i].im = (float)tw[i].im;
+        }
+        int rc = dalloc(c, &c->tw, tf.size() * sizeof(cpx<float>));
+        if (rc) return bail(rc);
+        e = hipMemcpy(c->tw, tf.data(), tf.size() * sizeof(cpx<float>), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "twiddle upload: %s", hipGetErrorString(e)));
+    const size_t state_bytes = (size_t)c->M * c->per * c->esz;
+    for (int i = 0; i < 7; ++i) {
+        int rc = dalloc(c, &c->buf[i], state_bytes);
+        if (rc) return bail(rc);
+    }
+    const size_t nb = (size_t)c->N * sizeof(double);
+    int rc = LISE_OK;
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->dens_cur), 3 * nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->dens_tmp), 3 * nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->V_cur), nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->V_tmp), nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->D_cur), 2 * nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->D_tmp), 2 * nb);
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->norms), (size_t)c->M * sizeof(double));
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->norms0), (size_t)c->M * sizeof(double));
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->bad), sizeof(int));
+    if (rc) return bail(rc);
+    e = hipMemset(c->bad, 0, sizeof(int));
+    if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipMemset: %s", hipGetErrorString(e)));
+    rc = configure(c);
+    if (rc) return bail(rc);
+    *out = c;
+    return LISE_OK;
+}
+
+int lise_set_qpwf(lise_ctx* c, int64_t first, int64_t count, const void* src, int32_t src_is_device) {
+    if (!c || !src) return LISE_E_ARG;
+    if (first < 0 || count < 1 || first + count > c->M) return fail(c, LISE_E_ARG, "qpwf range out of bounds");
+    const long long n = count * c->per;
+    void* dst = static_cast<char*>(c->buf[0]) + (size_t)first * c->per * c->esz;
+    if (c->hist || c->iy != 0) {
+        // a previous evolution moved y_n away from buffer 0: start over there,
+        // and require the whole set again
+        c->iy = 0;
+        c->n_set = 0;
+    }
+    if (c->prec == LISE_FP64) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)n * 16, src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 c->stream));
+    } else {
+        // stage float64 through device memory (p - c slot has room for M qpwfs in fp32: convert in pieces)
+        const long long piece = std::max<long long>(1, (64LL << 20) / 16);
+        void* stage = nullptr;
+        CHK(dalloc(c, &stage, (size_t)std::min<long long>(piece, n) * 16));
+        for (long long o = 0; o < n; o += piece) {
+            const long long k = std::min<long long>(piece, n - o);
+            const char* s = static_cast<const char*>(src) + (size_t)o * 16;
+            hipError_t e = hipMemcpyAsync(stage, s, (size_t)k * 16,
+                                          src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(c->stream);
+                dfree(&stage);
+                return fail(c, LISE_E_HIP, "qpwf upload: %s", hipGetErrorString(e));
+            }
+            hipLaunchKernelGGL((convert_kernel<float, double>), dim3(2048), dim3(kThreads), 0, c->stream,
+                               reinterpret_cast<const cpx<double>*>(stage),
+                               reinterpret_cast<cpx<float>*>(dst) + o, k);
+        }
+        (void)hipStreamSynchronize(c->stream);
+        dfree(&stage);
+        CHK(check_launch(c, "convert_kernel"));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_set = std::min<long long>(c->M, std::max<long long>(c->n_set, first + count));
+    c->hist = false;
+    c->dens_valid = false;
+    if (c->n_set >= c->M) {
+        if (c->prec == LISE_FP64) CHK(norms_t<double>(c, c->norms0));
+        else CHK(norms_t<float>(c, c->norms0));
+        c->norms0_valid = true;
+    }
+    return LISE_OK;
+}
+
+int lise_get_qpwf(lise_ctx* c, int64_t first, int64_t count, void* dst, int32_t dst_is_device) {
+    if (!c || !dst) return LISE_E_ARG;
+    if (first < 0 || count < 1 || first + count > c->M) return fail(c, LISE_E_ARG, "qpwf range out of bounds");
+    const long long n = count * c->per;
+    const char* src = static_cast<const char*>(c->buf[c->iy]) + (size_t)first * c->per * c->esz;
+    if (c->prec == LISE_FP64) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)n * 16, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return LISE_OK;
+    }
+    const long long piece = (64LL << 20) / 16;
+    void* stage = nullptr;
+    CHK(dalloc(c, &stage, (size_t)std::min<long long>(piece, n) * 16));
+    int rc = LISE_OK;
+    for (long long o = 0; o < n && rc == LISE_OK; o += piece) {
+        const long long k = std::min<long long>(piece, n - o);
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3(2048), dim3(kThreads), 0, c->stream,
+                           reinterpret_cast<const cpx<float>*>(src) + o, reinterpret_cast<cpx<double>*>(stage), k);
+        hipError_t e = hipMemcpyAsync(static_cast<char*>(dst) + (size_t)o * 16, stage, (size_t)k * 16,
+                                      dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = fail(c, LISE_E_HIP, "qpwf download: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dfree(&stage);
+    return rc;
+}
+
+int lise_apply_h(lise_ctx* c, int64_t first, int64_t count, void* out, int32_t out_is_device) {
+    if (!c || !out) return LISE_E_ARG;
+    if (first < 0 || count < 1 || first + count > c->M) return fail(c, LISE_E_ARG, "qpwf range out of bounds");
+    return c->prec == LISE_FP64 ? apply_h_t<double>(c, first, count, out, out_is_device)
+                                : apply_h_t<float>(c, first, count, out, out_is_device);
+}
+
+int lise_startup(lise_ctx* c, double dt) {
+    if (!c) return LISE_E_ARG;
+    if (!(std::isfinite(dt)) || dt == 0.0) return fail(c, LISE_E_ARG, "dt must be finite and non-zero");
+    return c->prec == LISE_FP64 ? startup_t<double>(c, dt) : startup_t<float>(c, dt);
+}
+
+int lise_step(lise_ctx* c, double dt, int64_t nsteps) {
+    if (!c) return LISE_E_ARG;
+    if (!(std::isfinite(dt)) || dt == 0.0) return fail(c, LISE_E_ARG, "dt must be finite and non-zero");
+    if (nsteps < 0) return fail(c, LISE_E_ARG, "nsteps must be >= 0");
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set");
+    return c->prec == LISE_FP64 ? step_t<double>(c, dt, nsteps) : step_t<float>(c, dt, nsteps);
+}
+
+int lise_densities(lise_ctx* c, double* n_out, double* kappa_out, int32_t out_is_device) {
+    if (!c) return LISE_E_ARG;
+    CHK(c->prec == LISE_FP64 ? ensure_fields_t<double>(c) : ensure_fields_t<float>(c));
+    const size_t nb = (size_t)c->N * sizeof(double);
+    const hipMemcpyKind kind = out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (n_out) HIPCHK(c, hipMemcpyAsync(n_out, c->dens_cur, nb, kind, c->stream));
+    if (kappa_out) {
+        // kappa is stored as two real planes; interleave through a small staging copy
+        std::vector<double> re(c->N), im(c->N);
+        HIPCHK(c, hipMemcpyAsync(re.data(), c->dens_cur + c->N, nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(im.data(), c->dens_cur + 2 * c->N, nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        std::vector<double> il(2 * c->N);
+        for (long long r = 0; r < c->N; ++r) {
+            il[2 * r] = re[r];
+            il[2 * r + 1] = im[r];
+        }
+        HIPCHK(c, hipMemcpyAsync(kappa_out, il.data(), 2 * nb, out_is_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost,
+                                 c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LISE_OK;
+}
+
+int lise_observables(lise_ctx* c, lise_obs* out) {
+    if (!c || !out) return LISE_E_ARG;
+    return c->prec == LISE_FP64 ? observables_t<double>(c, out) : observables_t<float>(c, out);
+}
+
+int lise_get_time(const lise_ctx* c, double* t, int64_t* step) {
+    if (!c) return LISE_E_ARG;
+    if (t) *t = c->t;
+    if (step) *step = c->step;
+    return LISE_OK;
+}
+
+int lise_set_time(lise_ctx* c, double t) {
+    if (!c || !std::isfinite(t)) return LISE_E_ARG;
+    c->t = t;
+    c->hist = false;
+    return LISE_OK;
+}
+
+int lise_set_stream(lise_ctx* c, void* hip_stream) {
+    if (!c) return LISE_E_ARG;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return LISE_OK;
+}
+
+int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
+    if (!c || !t) return LISE_E_ARG;
+    if (t->chunk_qpwf < 0 || t->jgroup < 0) return fail(c, LISE_E_ARG, "negative tuning value");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->chunk = t->chunk_qpwf;
+    if (t->jgroup > 0) c->jg = t->jgroup;
+    c->fused_pref = (t->fused < 0) ? 0 : 1;
+    return configure(c);
+}
+
+int lise_profile(lise_ctx* c, int32_t enable) {
+    if (!c) return LISE_E_ARG;
+    if (enable && c->prof.pool.empty()) {
+        c->prof.pool.resize(1 << 14);
+        for (auto& ev : c->prof.pool) HIPCHK(c, hipEventCreate(&ev));
+    }
+    c->prof.on = enable != 0;
+    return LISE_OK;
+}
+
+int lise_profile_read(lise_ctx* c, int32_t which, int64_t* launches, double* total_ms) {
+    if (!c || which < 0 || which > 3) return LISE_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& r : c->prof.recs) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+        c->prof.total_ms[r.cls] += ms;
+        c->prof.count[r.cls] += 1;
+    }
+    c->prof.recs.clear();
+    c->prof.used = 0;
+    if (launches) *launches = c->prof.count[which];
+    if (total_ms) *total_ms = c->prof.total_ms[which];
+    for (int k = 0; k < 4; ++k) {
+        c->prof.total_ms[k] = 0.0;
+        c->prof.count[k] = 0;
+    }
+    return LISE_OK;
+}
+
+int lise_memory(const lise_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return LISE_E_ARG;
+    long long b = 7LL * c->M * c->per * (long long)c->esz;
+    b += c->g_cap * c->per * (long long)c->esz;
+    b += (long long)c->slot_cap * 3 * c->N * 8;
+    b += 10LL * c->N * 8;
+    *bytes = b;
+    return LISE_OK;
+}
+
+const char* lise_last_error(const lise_ctx* c) { return c ? c->err : "null context"; }
+
+const char* lise_version(void) { return kVersion; }
+
+void lise_free(lise_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& p : c->buf) dfree(&p);
+    dfree(&c->G);
+    dfree(reinterpret_cast<void**>(&c->dpart));
+    dfree(reinterpret_cast<void**>(&c->dens_cur));
+    dfree(reinterpret_cast<void**>(&c->dens_tmp));
+    dfree(reinterpret_cast<void**>(&c->V_cur));
+    dfree(reinterpret_cast<void**>(&c->V_tmp));
+    dfree(reinterpret_cast<void**>(&c->D_cur));
+    dfree(reinterpret_cast<void**>(&c->D_tmp));
+    dfree(&c->tw);
+    dfree(reinterpret_cast<void**>(&c->red));
+    dfree(reinterpret_cast<void**>(&c->norms));
+    dfree(reinterpret_cast<void**>(&c->norms0));
+    dfree(reinterpret_cast<void**>(&c->bad));
+    for (auto& ev : c->prof.pool) (void)hipEventDestroy(ev);
+    delete c;
+}
+
+}  // extern "C"

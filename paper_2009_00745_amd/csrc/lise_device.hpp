@@ -1,0 +1,709 @@
+// Device code of the TDSLDA step for gfx950 (MI355X).
+//
+// The kinetic operator T = F^{-1} (|k|^2/2) F of Sec. "Discretization" has a
+// symbol that is a sum over axes, k^2 = kx^2 + ky^2 + kz^2, so
+//     T f = F_xy^{-1} [(kx^2 + ky^2)/2 F_xy f] + F_z^{-1} [kz^2/2 F_z f],
+// exactly (the transforms along the other axes cancel).  The step is built
+// from two kernels per Hamiltonian application:
+//   * kz_kernel: the z-axis term on xz-tiles (coalesced rows of x), written
+//     to a scratch buffer G;
+//   * kp_kernel: per xy-plane, the 2D FFT term in LDS, plus G, plus the local
+//     mixing of Eq. (tdslda) with V = U + U_ext and Delta, followed by the
+//     mode's epilogue (Taylor term, ABM phase 1 or ABM phase 2) and the
+//     float64 partial sums of the densities of Eq. (rho_t, nu_t).
+// When a whole lattice cube fits in LDS, kp_kernel also does the z axis and
+// G is not used ("fused" mode).
+//
+// FFTs are self-sorting mixed-radix Stockham transforms (radices 2,3,4,5,8)
+// ping-ponging between two LDS buffers, one radix-R butterfly per thread per
+// stage.  Forward uses exp(-2 pi i/n), inverse exp(+2 pi i/n) unnormalised;
+// the 1/n factors are folded into the k^2 multiply.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lise {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T r, T i) {
+    cpx<T> c;
+    c.re = r;
+    c.im = i;
+    return c;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.re, s * a.im); }
+template <typename T>
+__device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return mk(a.re, -a.im); }
+// multiply by i * sigma, sigma = +1 or -1
+template <typename T, int SIG>
+__device__ __forceinline__ cpx<T> mul_isig(cpx<T> a) {
+    return SIG > 0 ? mk(-a.im, a.re) : mk(a.im, -a.re);
+}
+
+// ---------------------------------------------------------------------------
+// FFT plan of one axis: radices of the stages and, per stage, the product p
+// of the earlier radices and the offset of its twiddles in the table.  The
+// twiddles of stage s are w(k, q) = exp(-2 pi i q k / (p R)), k < p,
+// 1 <= q < R, stored at tw[off + k (R-1) + q - 1].
+constexpr int kMaxStages = 7;
+struct AxisPlan {
+    int n;
+    int nst;
+    int radix[kMaxStages];
+    int p[kMaxStages];
+    int tw[kMaxStages];
+};
+
+// Lines of a batch of 1D transforms inside an LDS buffer.  Line L starts at
+// (L / lsub) * ls_out + (L % lsub) * ls_in; its elements are es apart.
+// lines_fast = 1 assigns consecutive threads to consecutive lines (strided
+// axes), 0 to consecutive butterflies of one line (the contiguous axis).
+struct LineMap {
+    int nlines, lsub, ls_in, ls_out, es, lines_fast;
+};
+
+// Small DFTs of size R on registers: b_s = sum_q a_q exp(SIG 2 pi i q s / R).
+template <typename T, int R, int SIG>
+struct SmallDft;
+
+template <typename T, int SIG>
+struct SmallDft<T, 2, SIG> {
+    static __device__ __forceinline__ void run(cpx<T>* a) {
+        cpx<T> t = a[0] - a[1];
+        a[0] = a[0] + a[1];
+        a[1] = t;
+    }
+};
+
+template <typename T, int SIG>
+struct SmallDft<T, 3, SIG> {
+    static __device__ __forceinline__ void run(cpx<T>* a) {
+        const T c = T(-0.5);
+        const T s = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+        cpx<T> t1 = a[1] + a[2];
+        cpx<T> t2 = a[0] + c * t1;
+        cpx<T> t3 = mul_isig<T, SIG>(s * (a[1] - a[2]));
+        a[0] = a[0] + t1;
+        a[1] = t2 + t3;
+        a[2] = t2 - t3;
+    }
+};
+
+template <typename T, int SIG>
+struct SmallDft<T, 4, SIG> {
+    static __device__ __forceinline__ void run(cpx<T>* a) {
+        cpx<T> s02 = a[0] + a[2], d02 = a[0] - a[2];
+        cpx<T> s13 = a[1] + a[3], d13 = mul_isig<T, SIG>(a[1] - a[3]);
+        a[0] = s02 + s13;
+        a[2] = s02 - s13;
+        a[1] = d02 + d13;
+        a[3] = d02 - d13;
+    }
+};
+
+template <typename T, int SIG>
+struct SmallDft<T, 5, SIG> {
+    static __device__ __forceinline__ void run(cpx<T>* a) {
+        // cos(2pi/5) = (sqrt5-1)/4, cos(4pi/5) = -(sqrt5+1)/4,
+        // sin(2pi/5) = sqrt(10+2sqrt5)/4, sin(4pi/5) = sqrt(10-2sqrt5)/4
+        const T c1 = T(0.30901699437494742410229341718282);
+        const T c2 = T(-0.80901699437494742410229341718282);
+        const T s1 = T(0.95105651629515357211643933337938);
+        const T s2 = T(0.58778525229247312916870595463907);
+        cpx<T> p14 = a[1] + a[4], m14 = a[1] - a[4];
+        cpx<T> p23 = a[2] + a[3], m23 = a[2] - a[3];
+        cpx<T> r1 = a[0] + c1 * p14 + c2 * p23;
+        cpx<T> r2 = a[0] + c2 * p14 + c1 * p23;
+        cpx<T> i1 = mul_isig<T, SIG>(s1 * m14 + s2 * m23);
+        cpx<T> i2 = mul_isig<T, SIG>(s2 * m14 - s1 * m23);
+        a[0] = a[0] + p14 + p23;
+        a[1] = r1 + i1;
+        a[4] = r1 - i1;
+        a[2] = r2 + i2;
+        a[3] = r2 - i2;
+    }
+};
+
+template <typename T, int SIG>
+struct SmallDft<T, 8, SIG> {
+    static __device__ __forceinline__ void run(cpx<T>* a) {
+        // even/odd split into two DFT-4s, then the radix-2 combination with
+        // w8^k = exp(SIG 2 pi i k / 8).
+        cpx<T> e[4] = {a[0], a[2], a[4], a[6]};
+        cpx<T> o[4] = {a[1], a[3], a[5], a[7]};
+        SmallDft<T, 4, SIG>::run(e);
+        SmallDft<T, 4, SIG>::run(o);
+        const T h = T(0.70710678118654752440084436210485);  // 1/sqrt2
+        cpx<T> o1 = h * (o[1] + mul_isig<T, SIG>(o[1]));     // w8^1 = (1 + i SIG)/sqrt2
+        cpx<T> o2 = mul_isig<T, SIG>(o[2]);                  // w8^2 = i SIG
+        cpx<T> o3 = h * (mul_isig<T, SIG>(o[3]) - o[3]);     // w8^3 = (-1 + i SIG)/sqrt2
+        a[0] = e[0] + o[0];
+        a[4] = e[0] - o[0];
+        a[1] = e[1] + o1;
+        a[5] = e[1] - o1;
+        a[2] = e[2] + o2;
+        a[6] = e[2] - o2;
+        a[3] = e[3] + o3;
+        a[7] = e[3] - o3;
+    }
+};
+
+// One Stockham stage of radix R over all lines of a LineMap:
+//   inputs  x[i + q m], m = n / R, twiddled by w(k, q), k = i mod p,
+//   outputs y[(i / p) p R + k + s p] = DFT_R of the twiddled inputs.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void fft_stage(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                          int n, int p, const cpx<T>* __restrict__ tw,
+                                          const LineMap lm, int tid, int nth) {
+    const int m = n / R;
+    const int total = lm.nlines * m;
+    for (int t = tid; t < total; t += nth) {
+        int L, i;
+        if (lm.lines_fast) {
+            L = t % lm.nlines;
+            i = t / lm.nlines;
+        } else {
+            i = t % m;
+            L = t / m;
+        }
+        const int base = (L / lm.lsub) * lm.ls_out + (L % lm.lsub) * lm.ls_in;
+        const int k = i % p;
+        cpx<T> a[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] = src[base + (i + q * m) * lm.es];
+        if (p > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                cpx<T> w = tw[k * (R - 1) + (q - 1)];
+                if (INV) w.im = -w.im;
+                a[q] = a[q] * w;
+            }
+        }
+        SmallDft<T, R, INV ? 1 : -1>::run(a);
+        const int j = (i / p) * p * R + k;
+#pragma unroll
+        for (int s = 0; s < R; ++s) dst[base + (j + s * p) * lm.es] = a[s];
+    }
+}
+
+// Full 1D transform along one axis; returns the buffer holding the result.
+template <typename T, bool INV>
+__device__ cpx<T>* fft_axis(cpx<T>* src, cpx<T>* dst, const AxisPlan& pl,
+                            const cpx<T>* __restrict__ tw, const LineMap lm, int tid, int nth) {
+    for (int s = 0; s < pl.nst; ++s) {
+        const int R = pl.radix[s];
+        const int p = pl.p[s];
+        const cpx<T>* t = tw + pl.tw[s];
+        switch (R) {
+            case 2: fft_stage<T, 2, INV>(src, dst, pl.n, p, t, lm, tid, nth); break;
+            case 3: fft_stage<T, 3, INV>(src, dst, pl.n, p, t, lm, tid, nth); break;
+            case 4: fft_stage<T, 4, INV>(src, dst, pl.n, p, t, lm, tid, nth); break;
+            case 5: fft_stage<T, 5, INV>(src, dst, pl.n, p, t, lm, tid, nth); break;
+            default: fft_stage<T, 8, INV>(src, dst, pl.n, p, t, lm, tid, nth); break;
+        }
+        __syncthreads();
+        cpx<T>* x = src;
+        src = dst;
+        dst = x;
+    }
+    return src;
+}
+
+__device__ __forceinline__ int signed_mode(int i, int n) { return (2 * i < n) ? i : i - n; }
+
+// ---------------------------------------------------------------------------
+// Kernel arguments
+
+enum KpMode { KP_APPLY = 0, KP_ABM1 = 1, KP_ABM2 = 2, KP_KINETIC = 3 };
+
+template <typename T>
+struct KPArgs {
+    int nx, ny, nz, C, npair;
+    int zb;          // xy-planes per workgroup (nz when fused)
+    int jg;          // qpwfs walked by one workgroup
+    int kcount;      // qpwfs in this launch
+    long long j0;    // first qpwf (global index) of this launch
+    int fused;       // 1: z axis in LDS too, G unused
+    AxisPlan px, py, pz;
+    const cpx<T>* tw;
+    T cx, cy, cz;    // k_a^2 / 2 / (transform size) = c_a * m_a^2
+    const double* V;
+    const double* D;  // complex, interleaved
+    double mu_a[2], mu_b[2];
+    int sgn[2], ca[2], cb[2];
+    double w;         // density weight of a pair
+    const cpx<T>* in;
+    const cpx<T>* G;  // indexed by the qpwf index within the launch
+    // KP_APPLY
+    cpx<T>* out;
+    cpx<T>* acc;
+    cpx<T>* deriv;
+    int acc_from_in;
+    double coef_re, coef_im;
+    // KP_ABM1: a1 = y_{n-1}, a2 = y'_{n-1}, a3 = y'_{n-2}, a4 = y'_{n-3} -> m,
+    //          a5 = d_n, a6 -> y'_n
+    // KP_ABM2: in = m, a1 = d_n -> d_{n+1}, a2 = y_n, a3 = y_{n-1} -> y_{n+1},
+    //          a4 = y'_n, a5 = y'_{n-1}, a6 = y'_{n-2}
+    cpx<T>* a1;
+    cpx<T>* a2;
+    cpx<T>* a3;
+    cpx<T>* a4;
+    cpx<T>* a5;
+    cpx<T>* a6;
+    double dt;
+    double* dpart;    // [slot][3][N] float64 density partial sums
+    int dens_src;     // 0: none, 1: the produced vector (m, y_{n+1}, acc or out)
+    int accumulate;   // 0: store partials, 1: add to them
+    double* epart;    // KP_KINETIC: one float64 per workgroup
+};
+
+template <typename T, int MODE, int PPT>
+__global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* bufA = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int nth = blockDim.x;
+    const int tid = threadIdx.x;
+    const int nxy = a.nx * a.ny;
+    const int P = a.zb * nxy;                  // points of one component in this WG
+    cpx<T>* bufB = bufA + 2 * P;
+    const int z0 = blockIdx.x * a.zb;
+    const long long N = (long long)nxy * a.nz;
+    const int jbeg = blockIdx.y * a.jg;
+    const int jend = min(a.kcount, jbeg + a.jg);
+
+    double dn[PPT], dkr[PPT], dki[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) dn[i] = dkr[i] = dki[i] = 0.0;
+    double ekin = 0.0;
+
+    const T cdt = T(a.dt / 48.0);
+    const cpx<T> coef = mk(T(a.coef_re), T(a.coef_im));
+
+    // line maps of the three axes over the two LDS planes-stacks
+    const LineMap lmx = {2 * a.zb * a.ny, 2 * a.zb * a.ny, a.nx, 0, 1, 0};
+    const LineMap lmy = {2 * a.zb * a.nx, a.nx, 1, nxy, a.nx, 1};
+    const LineMap lmz = {2 * nxy, nxy, 1, a.nz * nxy, nxy, 1};
+
+    for (int jl = jbeg; jl < jend; ++jl) {
+        const long long jgl = a.j0 + jl;
+        for (int pr = 0; pr < a.npair; ++pr) {
+            const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z0) * (long long)nxy;
+            const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z0) * (long long)nxy;
+            cpx<T> fa[PPT], fb[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int q = tid + i * nth;
+                if (q < P) {
+                    fa[i] = a.in[offa + q];
+                    fb[i] = a.in[offb + q];
+                    bufA[q] = fa[i];
+                    bufA[P + q] = fb[i];
+                }
+            }
+            __syncthreads();
+            // forward transforms (x, y, and z when fused)
+            cpx<T>* r = fft_axis<T, false>(bufA, bufB, a.px, a.tw, lmx, tid, nth);
+            cpx<T>* o = (r == bufA) ? bufB : bufA;
+            r = fft_axis<T, false>(r, o, a.py, a.tw, lmy, tid, nth);
+            o = (r == bufA) ? bufB : bufA;
+            if (a.fused) {
+                r = fft_axis<T, false>(r, o, a.pz, a.tw, lmz, tid, nth);
+                o = (r == bufA) ? bufB : bufA;
+            }
+            // multiply by k^2/2 divided by the transform size
+            for (int e = tid; e < 2 * P; e += nth) {
+                const int q = e % P;
+                const int x = q % a.nx;
+                const int y = (q / a.nx) % a.ny;
+                const int mx = signed_mode(x, a.nx), my = signed_mode(y, a.ny);
+                T f = a.cx * T(mx * mx) + a.cy * T(my * my);
+                if (a.fused) {
+                    const int mz = signed_mode(q / nxy, a.nz);
+                    f += a.cz * T(mz * mz);
+                }
+                r[e] = f * r[e];
+            }
+            __syncthreads();
+            if (a.fused) {
+                r = fft_axis<T, true>(r, o, a.pz, a.tw, lmz, tid, nth);
+                o = (r == bufA) ? bufB : bufA;
+            }
+            r = fft_axis<T, true>(r, o, a.py, a.tw, lmy, tid, nth);
+            o = (r == bufA) ? bufB : bufA;
+            r = fft_axis<T, true>(r, o, a.px, a.tw, lmx, tid, nth);
+
+            const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
+            const T sg = T(a.sgn[pr]);
+            const long long gofa = offa, gofb = offb;   // element offsets of this plane stack
+            const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
+            const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int q = tid + i * nth;
+                if (q >= P) continue;
+                cpx<T> Ta = r[q], Tb = r[P + q];
+                if (!a.fused) {
+                    Ta = Ta + a.G[lofa + q];
+                    Tb = Tb + a.G[lofb + q];
+                }
+                const long long rpt = (long long)z0 * nxy + q;
+                if (MODE == KP_KINETIC) {
+                    ekin += a.w * (double(fb[i].re) * double(Tb.re) + double(fb[i].im) * double(Tb.im));
+                    continue;
+                }
+                const T Vr = T(a.V[rpt]);
+                const cpx<T> Dl = mk(T(sg * a.D[2 * rpt]), T(sg * a.D[2 * rpt + 1]));
+                // H u = (h - mu_a) u + s Delta v ;  H v = s Delta^* u - (h - mu_b) v
+                const cpx<T> Ha = Ta + (Vr - mua) * fa[i] + Dl * fb[i];
+                const cpx<T> Hb = conjg(Dl) * fa[i] - (Tb + (Vr - mub) * fb[i]);
+                const long long ea = gofa + q, eb = gofb + q;
+                cpx<T> va, vb;   // vector whose densities are accumulated
+                if (MODE == KP_APPLY) {
+                    const cpx<T> oa = coef * Ha, ob = coef * Hb;
+                    if (a.deriv) {
+                        a.deriv[ea] = mk(Ha.im, -Ha.re);
+                        a.deriv[eb] = mk(Hb.im, -Hb.re);
+                    }
+                    va = oa;
+                    vb = ob;
+                    if (a.acc) {
+                        const cpx<T> pa = a.acc_from_in ? fa[i] : a.acc[ea];
+                        const cpx<T> pb = a.acc_from_in ? fb[i] : a.acc[eb];
+                        va = pa + oa;
+                        vb = pb + ob;
+                        a.acc[ea] = va;
+                        a.acc[eb] = vb;
+                    }
+                    if (a.out) {
+                        a.out[ea] = oa;
+                        a.out[eb] = ob;
+                    }
+                } else if (MODE == KP_ABM1) {
+                    // y'_n = -i H y_n
+                    const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);
+                    // p = (y_n + y_{n-1})/2 + dt/48 (119 y'_n - 99 y'_{n-1} + 69 y'_{n-2} - 17 y'_{n-3})
+                    // m = p - 161/170 (p_n - c_n)
+                    const cpx<T> pa = T(0.5) * (fa[i] + a.a1[ea]) +
+                                      cdt * (T(119) * da - T(99) * a.a2[ea] + T(69) * a.a3[ea] - T(17) * a.a4[ea]);
+                    const cpx<T> pb = T(0.5) * (fb[i] + a.a1[eb]) +
+                                      cdt * (T(119) * db - T(99) * a.a2[eb] + T(69) * a.a3[eb] - T(17) * a.a4[eb]);
+                    va = pa - T(161.0 / 170.0) * a.a5[ea];
+                    vb = pb - T(161.0 / 170.0) * a.a5[eb];
+                    a.a6[ea] = da;
+                    a.a6[eb] = db;
+                    a.a4[ea] = va;
+                    a.a4[eb] = vb;
+                } else {  // KP_ABM2
+                    const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
+                    const cpx<T> dna = a.a1[ea], dnb = a.a1[eb];
+                    const cpx<T> pa = fa[i] + T(161.0 / 170.0) * dna;              // p = m + 161/170 d_n
+                    const cpx<T> pb = fb[i] + T(161.0 / 170.0) * dnb;
+                    // c = (y_n + y_{n-1})/2 + dt/48 (17 m' + 51 y'_n + 3 y'_{n-1} + y'_{n-2})
+                    const cpx<T> cA = T(0.5) * (a.a2[ea] + a.a3[ea]) +
+                                      cdt * (T(17) * ma + T(51) * a.a4[ea] + T(3) * a.a5[ea] + a.a6[ea]);
+                    const cpx<T> cB = T(0.5) * (a.a2[eb] + a.a3[eb]) +
+                                      cdt * (T(17) * mb + T(51) * a.a4[eb] + T(3) * a.a5[eb] + a.a6[eb]);
+                    const cpx<T> dA = pa - cA, dB = pb - cB;                          // d_{n+1} = p - c
+                    va = cA + T(9.0 / 170.0) * dA;                                    // y_{n+1}
+                    vb = cB + T(9.0 / 170.0) * dB;
+                    a.a1[ea] = dA;
+                    a.a1[eb] = dB;
+                    a.a3[ea] = va;
+                    a.a3[eb] = vb;
+                }
+                if (a.dens_src) {
+                    const double br = double(vb.re), bi = double(vb.im);
+                    const double ar = double(va.re), ai = double(va.im);
+                    dn[i] += a.w * (br * br + bi * bi);
+                    const double hs = 0.5 * a.w * double(a.sgn[pr]);
+                    dkr[i] += hs * (br * ar + bi * ai);   // Re(conj(b) a)
+                    dki[i] += hs * (br * ai - bi * ar);   // Im(conj(b) a)
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (MODE == KP_KINETIC) {
+        // workgroup reduction of the kinetic partial sum
+        double* red = reinterpret_cast<double*>(smem_raw);
+        red[tid] = ekin;
+        __syncthreads();
+        for (int s = nth / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) a.epart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        return;
+    }
+    if (a.dens_src) {
+        double* base = a.dpart + (long long)blockIdx.y * 3 * N + (long long)z0 * nxy;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int q = tid + i * nth;
+            if (q >= P) continue;
+            if (a.accumulate) {
+                base[q] += dn[i];
+                base[N + q] += dkr[i];
+                base[2 * N + q] += dki[i];
+            } else {
+                base[q] = dn[i];
+                base[N + q] = dkr[i];
+                base[2 * N + q] = dki[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-axis kinetic term on xz-tiles: G = F_z^{-1} [kz^2/2 F_z f] / nz
+
+template <typename T>
+struct KZArgs {
+    int nx, ny, nz, C, yb;
+    long long j0;
+    AxisPlan pz;
+    const cpx<T>* tw;
+    T cz;
+    const cpx<T>* in;
+    cpx<T>* G;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) kz_kernel(const KZArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* bufA = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int row = a.yb * a.nx;             // points of one z-row of the tile
+    const int P = a.nz * row;
+    cpx<T>* bufB = bufA + P;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int y0 = blockIdx.x * a.yb;
+    const long long jc = blockIdx.y;         // local qpwf * C + component
+    const long long nxy = (long long)a.nx * a.ny;
+    const long long gbase = ((a.j0 * a.C + jc) * a.nz) * nxy + (long long)y0 * a.nx;
+    const long long lbase = (jc * a.nz) * nxy + (long long)y0 * a.nx;
+    for (int e = tid; e < P; e += nth) {
+        const int z = e / row, rr = e % row;
+        bufA[e] = a.in[gbase + z * nxy + rr];
+    }
+    __syncthreads();
+    const LineMap lm = {row, row, 1, 0, row, 1};
+    cpx<T>* r = fft_axis<T, false>(bufA, bufB, a.pz, a.tw, lm, tid, nth);
+    cpx<T>* o = (r == bufA) ? bufB : bufA;
+    for (int e = tid; e < P; e += nth) {
+        const int mz = signed_mode(e / row, a.nz);
+        r[e] = (a.cz * T(mz * mz)) * r[e];
+    }
+    __syncthreads();
+    r = fft_axis<T, true>(r, o, a.pz, a.tw, lm, tid, nth);
+    for (int e = tid; e < P; e += nth) {
+        const int z = e / row, rr = e % row;
+        a.G[lbase + z * nxy + rr] = r[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Densities straight from a state (no Hamiltonian), one thread per point,
+// each thread walking jg qpwfs; partial sums per slot.
+
+template <typename T>
+__global__ void __launch_bounds__(256) dens_partial_kernel(const cpx<T>* __restrict__ in, int C, long long N,
+                                                           long long M, int jg, double w,
+                                                           double* __restrict__ dpart) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const long long j0 = (long long)blockIdx.y * jg;
+    const long long j1 = min(M, j0 + jg);
+    double n = 0.0, kr = 0.0, ki = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        for (int pr = 0; pr < C / 2; ++pr) {
+            const int ca = (C == 2) ? 0 : pr;
+            const int cb = (C == 2) ? 1 : 3 - pr;
+            const double s = (pr == 0) ? 1.0 : -1.0;
+            const cpx<T> u = in[(j * C + ca) * N + r];
+            const cpx<T> v = in[(j * C + cb) * N + r];
+            const double br = double(v.re), bi = double(v.im), ar = double(u.re), ai = double(u.im);
+            n += w * (br * br + bi * bi);
+            kr += 0.5 * w * s * (br * ar + bi * ai);
+            ki += 0.5 * w * s * (br * ai - bi * ar);
+        }
+    }
+    double* base = dpart + (long long)blockIdx.y * 3 * N;
+    base[r] = n;
+    base[N + r] = kr;
+    base[2 * N + r] = ki;
+}
+
+// ---------------------------------------------------------------------------
+// Sum of the density partials (fixed order: deterministic), optional average
+// with another density set (series-expansion corrector), and the local
+// fields U + U_ext and Delta.
+
+struct FieldParams {
+    int nx, ny, nz;
+    double a;
+    double beta, g;
+    int frozen;
+    double U0, D0re, D0im;
+    double extA, extw, r0x, r0y, r0z, t_on;
+};
+
+__device__ __forceinline__ double ext_ramp(const FieldParams& f, double t) {
+    if (f.t_on > 0.0 && t < f.t_on) {
+        const double s = sin(M_PI * fmax(t, 0.0) / (2.0 * f.t_on));
+        return s * s;
+    }
+    return 1.0;
+}
+
+__device__ __forceinline__ double min_image(double d, double L) { return d - L * rint(d / L); }
+
+__device__ __forceinline__ double ext_potential(const FieldParams& f, long long r, double ramp) {
+    if (f.extA == 0.0) return 0.0;
+    const int x = int(r % f.nx);
+    const int y = int((r / f.nx) % f.ny);
+    const int z = int(r / ((long long)f.nx * f.ny));
+    const double dx = min_image(x * f.a - f.r0x, f.nx * f.a);
+    const double dy = min_image(y * f.a - f.r0y, f.ny * f.a);
+    const double dz = min_image(z * f.a - f.r0z, f.nz * f.a);
+    const double d2 = dz * dz + dy * dy + dx * dx;
+    return f.extA * ramp * exp(-d2 / (2.0 * f.extw * f.extw));
+}
+
+__global__ void __launch_bounds__(256) fields_kernel(const double* __restrict__ dpart, int nslots, long long N,
+                                                     const double* __restrict__ avg_with,
+                                                     double* __restrict__ dens_out, double* __restrict__ V,
+                                                     double* __restrict__ D, FieldParams fp, double t,
+                                                     int* __restrict__ bad) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    double n, kr, ki;
+    if (nslots > 0) {
+        n = kr = ki = 0.0;
+        for (int s = 0; s < nslots; ++s) {
+            const double* b = dpart + (long long)s * 3 * N;
+            n += b[r];
+            kr += b[N + r];
+            ki += b[2 * N + r];
+        }
+    } else {
+        n = dens_out[r];
+        kr = dens_out[N + r];
+        ki = dens_out[2 * N + r];
+    }
+    if (avg_with) {
+        n = 0.5 * (n + avg_with[r]);
+        kr = 0.5 * (kr + avg_with[N + r]);
+        ki = 0.5 * (ki + avg_with[2 * N + r]);
+    }
+    if (!(isfinite(n) && isfinite(kr) && isfinite(ki))) atomicOr(bad, 1);
+    dens_out[r] = n;
+    dens_out[N + r] = kr;
+    dens_out[2 * N + r] = ki;
+    double U;
+    double dre, dim;
+    if (fp.frozen) {
+        U = fp.U0;
+        dre = fp.D0re;
+        dim = fp.D0im;
+    } else {
+        const double c = cbrt(n);
+        U = fp.beta * c * c;
+        dre = -fp.g * kr;
+        dim = -fp.g * ki;
+    }
+    V[r] = U + ext_potential(fp, r, ext_ramp(fp, t));
+    D[2 * r] = dre;
+    D[2 * r + 1] = dim;
+}
+
+// Observables of the fields: per-block partial sums of
+// [n, n x, n y, n z, 3/5 beta n^{5/3}, g |kappa|^2, U_ext n, |Delta| n].
+constexpr int kNObs = 8;
+__global__ void __launch_bounds__(256) obs_fields_kernel(const double* __restrict__ dens,
+                                                         const double* __restrict__ D, long long N,
+                                                         FieldParams fp, double t,
+                                                         double* __restrict__ part) {
+    __shared__ double red[kNObs][256];
+    const int tid = threadIdx.x;
+    double acc[kNObs] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double ramp = ext_ramp(fp, t);
+    for (long long r = (long long)blockIdx.x * blockDim.x + tid; r < N; r += (long long)gridDim.x * blockDim.x) {
+        const double n = dens[r], kr = dens[N + r], ki = dens[2 * N + r];
+        const int x = int(r % fp.nx);
+        const int y = int((r / fp.nx) % fp.ny);
+        const int z = int(r / ((long long)fp.nx * fp.ny));
+        const double c = cbrt(n);
+        acc[0] += n;
+        acc[1] += n * (x * fp.a);
+        acc[2] += n * (y * fp.a);
+        acc[3] += n * (z * fp.a);
+        acc[4] += 0.6 * fp.beta * c * c * c * c * c;
+        acc[5] += fp.g * (kr * kr + ki * ki);
+        acc[6] += ext_potential(fp, r, ramp) * n;
+        acc[7] += sqrt(D[2 * r] * D[2 * r] + D[2 * r + 1] * D[2 * r + 1]) * n;
+    }
+    for (int k = 0; k < kNObs; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < kNObs; ++k) red[k][tid] += red[k][tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < kNObs; ++k) part[blockIdx.x * kNObs + k] = red[k][0];
+}
+
+// Norm of each qpwf: sum over components and points of |psi|^2 (float64).
+template <typename T>
+__global__ void __launch_bounds__(256) norm_kernel(const cpx<T>* __restrict__ in, long long per,
+                                                   double* __restrict__ norms) {
+    __shared__ double red[256];
+    const long long j = blockIdx.x;
+    const cpx<T>* p = in + j * per;
+    double s = 0.0;
+    for (long long e = threadIdx.x; e < per; e += blockDim.x) {
+        const double re = double(p[e].re), im = double(p[e].im);
+        s += re * re + im * im;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[j] = red[0];
+}
+
+// Precision conversion between the float64 interface and the state.
+template <typename TO, typename TI>
+__global__ void __launch_bounds__(256) convert_kernel(const cpx<TI>* __restrict__ in, cpx<TO>* __restrict__ out,
+                                                      long long n) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const cpx<TI> v = in[e];
+        out[e] = mk(TO(v.re), TO(v.im));
+    }
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ p, long long n) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
+
+}  // namespace lise

@@ -1,0 +1,224 @@
+"""Python binding of liblise (ctypes, argument marshalling only).
+
+Every computation runs in the HIP kernels of liblise.so.  The binding loads
+the in-tree library and raises if it is missing; there is no fallback.
+Device buffers passed in or out may be PyTorch tensors (their data_ptr is
+used) or NumPy arrays (host memory).
+"""
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblise.so")
+
+LISE_FP64, LISE_FP32 = 0, 1
+ERRORS = {0: "OK", -1: "LISE_E_ARG", -2: "LISE_E_NOMEM", -3: "LISE_E_UNSUPPORTED",
+          -4: "LISE_E_HIP", -5: "LISE_E_STATE", -6: "LISE_E_NAN"}
+
+# every entry point declared in include/lise.h
+SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_startup",
+           "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
+           "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
+           "lise_memory", "lise_last_error", "lise_version", "lise_free"]
+
+
+class Lattice(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("reserved", ct.c_int32), ("a", ct.c_double)]
+
+
+class Functional(ct.Structure):
+    _fields_ = [("ncomp", ct.c_int32), ("precision", ct.c_int32),
+                ("mu_up", ct.c_double), ("mu_dn", ct.c_double),
+                ("beta", ct.c_double), ("g", ct.c_double), ("w", ct.c_double),
+                ("frozen", ct.c_int32), ("reserved", ct.c_int32),
+                ("U0", ct.c_double), ("Delta0_re", ct.c_double), ("Delta0_im", ct.c_double),
+                ("ext_A", ct.c_double), ("ext_w", ct.c_double),
+                ("ext_r0", ct.c_double * 3), ("ext_t_on", ct.c_double)]
+
+
+class Obs(ct.Structure):
+    _fields_ = [("t", ct.c_double), ("step", ct.c_int64),
+                ("N", ct.c_double), ("E", ct.c_double), ("E_kin", ct.c_double),
+                ("E_int", ct.c_double), ("E_pair", ct.c_double), ("E_ext", ct.c_double),
+                ("mean_abs_delta", ct.c_double), ("r_cm", ct.c_double * 3),
+                ("norm_drift_max", ct.c_double), ("norm_drift_mean", ct.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["r_cm"] = list(self.r_cm)
+        return d
+
+
+class Tuning(ct.Structure):
+    _fields_ = [("chunk_qpwf", ct.c_int32), ("jgroup", ct.c_int32),
+                ("fused", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load liblise.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblise.so not found at {path}: build it with "
+                           "`python -m paper_2009_00745_amd.build` (no CPU fallback exists)")
+    lib = ct.CDLL(path)
+    P = ct.c_void_p
+    sig = {
+        "lise_init": ([ct.POINTER(P), ct.POINTER(Lattice), ct.c_int64, ct.POINTER(Functional), P], ct.c_int),
+        "lise_set_qpwf": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
+        "lise_get_qpwf": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
+        "lise_apply_h": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
+        "lise_startup": ([P, ct.c_double], ct.c_int),
+        "lise_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
+        "lise_densities": ([P, P, P, ct.c_int32], ct.c_int),
+        "lise_observables": ([P, ct.POINTER(Obs)], ct.c_int),
+        "lise_get_time": ([P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)], ct.c_int),
+        "lise_set_time": ([P, ct.c_double], ct.c_int),
+        "lise_set_stream": ([P, P], ct.c_int),
+        "lise_set_tuning": ([P, ct.POINTER(Tuning)], ct.c_int),
+        "lise_profile": ([P, ct.c_int32], ct.c_int),
+        "lise_profile_read": ([P, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)], ct.c_int),
+        "lise_memory": ([P, ct.POINTER(ct.c_int64)], ct.c_int),
+        "lise_last_error": ([P], ct.c_char_p),
+        "lise_version": ([], ct.c_char_p),
+        "lise_free": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+class LiseError(RuntimeError):
+    pass
+
+
+def _ptr(x):
+    """(address, is_device) of a torch tensor or a NumPy array."""
+    if hasattr(x, "data_ptr"):
+        return ct.c_void_p(x.data_ptr()), int(x.is_cuda)
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return ct.c_void_p(x.ctypes.data), 0
+    raise TypeError("expected a torch tensor or a numpy array")
+
+
+class Context:
+    """One TDSLDA system on the current HIP device (see include/lise.h)."""
+
+    def __init__(self, lattice, n_qpwf, functional, stream=None):
+        self.lib = load_library()
+        self.nx, self.ny, self.nz = lattice.nx, lattice.ny, lattice.nz
+        self.a = lattice.a
+        self.M = int(n_qpwf)
+        self.C = int(functional.ncomp)
+        self.N = self.nx * self.ny * self.nz
+        lat = Lattice(lattice.nx, lattice.ny, lattice.nz, 0, lattice.a)
+        f = functional
+        d0 = complex(f.Delta0)
+        fn = Functional(f.ncomp, f.precision, f.mu_up, f.mu_dn, f.beta, f.g, f.w,
+                        int(f.frozen), 0, f.U0, d0.real, d0.imag, f.ext_A, f.ext_w,
+                        (ct.c_double * 3)(*f.ext_r0), f.ext_t_on)
+        self._h = ct.c_void_p()
+        rc = self.lib.lise_init(ct.byref(self._h), ct.byref(lat), self.M, ct.byref(fn),
+                                ct.c_void_p(stream or 0))
+        if rc != 0:
+            raise LiseError(f"lise_init failed: {ERRORS.get(rc, rc)}")
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.lise_last_error(self._h).decode()
+            raise LiseError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+    def close(self):
+        if self._h:
+            self.lib.lise_free(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_qpwf(self, first, data):
+        p, dev = _ptr(data)
+        count = data.shape[0]
+        self._check(self.lib.lise_set_qpwf(self._h, first, count, p, dev), "lise_set_qpwf")
+
+    def get_qpwf(self, first, count, out=None):
+        if out is None:
+            out = np.empty((count, self.C, self.nz, self.ny, self.nx), dtype=np.complex128)
+        p, dev = _ptr(out)
+        self._check(self.lib.lise_get_qpwf(self._h, first, count, p, dev), "lise_get_qpwf")
+        return out
+
+    def apply_h(self, first, count, out=None):
+        if out is None:
+            out = np.empty((count, self.C, self.nz, self.ny, self.nx), dtype=np.complex128)
+        p, dev = _ptr(out)
+        self._check(self.lib.lise_apply_h(self._h, first, count, p, dev), "lise_apply_h")
+        return out
+
+    def startup(self, dt):
+        self._check(self.lib.lise_startup(self._h, dt), "lise_startup")
+
+    def step(self, dt, nsteps):
+        self._check(self.lib.lise_step(self._h, dt, nsteps), "lise_step")
+
+    def densities(self):
+        n = np.empty((self.nz, self.ny, self.nx), dtype=np.float64)
+        k = np.empty((self.nz, self.ny, self.nx), dtype=np.complex128)
+        self._check(self.lib.lise_densities(self._h, ct.c_void_p(n.ctypes.data),
+                                            ct.c_void_p(k.ctypes.data), 0), "lise_densities")
+        return n, k
+
+    def observables(self):
+        o = Obs()
+        self._check(self.lib.lise_observables(self._h, ct.byref(o)), "lise_observables")
+        return o.as_dict()
+
+    def time(self):
+        t = ct.c_double()
+        s = ct.c_int64()
+        self._check(self.lib.lise_get_time(self._h, ct.byref(t), ct.byref(s)), "lise_get_time")
+        return t.value, s.value
+
+    def set_time(self, t):
+        self._check(self.lib.lise_set_time(self._h, t), "lise_set_time")
+
+    def set_stream(self, stream):
+        self._check(self.lib.lise_set_stream(self._h, ct.c_void_p(stream or 0)), "lise_set_stream")
+
+    def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0):
+        t = Tuning(chunk_qpwf, jgroup, fused, 0)
+        self._check(self.lib.lise_set_tuning(self._h, ct.byref(t)), "lise_set_tuning")
+
+    def profile(self, enable):
+        self._check(self.lib.lise_profile(self._h, int(enable)), "lise_profile")
+
+    def profile_read(self, which):
+        n = ct.c_int64()
+        ms = ct.c_double()
+        self._check(self.lib.lise_profile_read(self._h, which, ct.byref(n), ct.byref(ms)),
+                    "lise_profile_read")
+        return n.value, ms.value
+
+    def memory(self):
+        b = ct.c_int64()
+        self._check(self.lib.lise_memory(self._h, ct.byref(b)), "lise_memory")
+        return b.value
+
+
+def version():
+    return load_library().lise_version().decode()

@@ -1,0 +1,300 @@
+"""GPU parity: the HIP library (through its C-ABI) against the CPU FP64 oracle.
+
+Every case prints its name and shape before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lise():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    import paper_2009_00745_amd as lise_mod
+    lise_mod.load_library()
+    return lise_mod
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def random_state(lat, M, C, seed):
+    rng = np.random.default_rng(seed)
+    shp = (M, C, lat.nz, lat.ny, lat.nx)
+    psi = rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+    psi /= np.sqrt(np.sum(np.abs(psi) ** 2, axis=(1, 2, 3, 4), keepdims=True) * lat.a ** 3)
+    return psi
+
+
+APPLY_CASES = [
+    # (nx, ny, nz, a, C, M, precision, tuning)
+    (4, 4, 4, 1.0, 2, 5, 0, {}),
+    (8, 8, 8, 1.0, 2, 7, 0, {}),
+    (8, 8, 8, 1.0, 2, 7, 0, {"fused": -1}),
+    (6, 10, 8, 0.8, 2, 4, 0, {}),
+    (6, 10, 8, 0.8, 2, 9, 0, {"fused": -1, "chunk_qpwf": 4, "jgroup": 3}),
+    (5, 3, 4, 1.2, 2, 3, 0, {}),
+    (12, 12, 12, 1.0, 4, 3, 0, {}),
+    (20, 20, 20, 1.0, 2, 3, 0, {}),
+    (24, 16, 20, 1.0, 4, 2, 0, {}),
+    (32, 32, 32, 1.0, 2, 3, 0, {}),
+    (16, 16, 16, 1.0, 2, 6, 1, {}),
+    (48, 48, 48, 1.0, 2, 2, 1, {}),
+]
+
+
+@pytest.mark.parametrize("case", APPLY_CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"_C{c[4]}_p{c[6]}_{c[7]}")
+def test_apply_h_matches_oracle(lise, case):
+    nx, ny, nz, a, C, M, prec, tun = case
+    say(f"apply_h {nx}x{ny}x{nz} C={C} M={M} prec={prec} tuning={tun}")
+    lat = wl.Lattice(nx, ny, nz, a)
+    fn = wl.Functional(ncomp=C, mu_up=0.4, mu_dn=0.25 if C == 4 else 0.4, beta=0.37, g=1.7, w=2.0 if C == 2 else 1.0,
+                       ext_A=-0.2, ext_w=1.5, ext_r0=(1.0 * a, 2.0 * a, 0.0), ext_t_on=0.0, precision=prec)
+    psi = random_state(lat, M, C, seed=nx * 100 + ny * 10 + nz + M)
+    ctx = lise.Context(lat, M, fn)
+    if tun:
+        ctx.set_tuning(**tun)
+    ctx.set_qpwf(0, psi)
+    got = ctx.apply_h(0, M)
+    V, D = oracle.hamiltonian_of(psi, lat, fn, 0.0)
+    ref = oracle.apply_h(psi, V, D, lat, fn)
+    tol = 1e-12 if prec == 0 else 3e-6
+    err = rel_max(got, ref)
+    say(f"  rel max err {err:.3e}")
+    assert err < tol
+    # a sub-range
+    if M > 2:
+        sub = ctx.apply_h(1, M - 2)
+        assert rel_max(sub, ref[1:M - 1]) < tol
+    n, k = ctx.densities()
+    n0, k0 = oracle.densities(psi, fn)
+    dtol = 1e-13 if prec == 0 else 1e-6
+    assert rel_max(n, n0) < dtol and rel_max(k, k0) < dtol
+    ctx.close()
+
+
+def run_pair(lise, w, nsteps, tuning=None, psi=None):
+    psi = w.qpwfs() if psi is None else psi
+    ctx = lise.Context(w.lattice, w.M, w.functional)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    ctx.set_qpwf(0, psi)
+    ctx.step(w.dt, nsteps)
+    got = ctx.get_qpwf(0, w.M)
+    n, k = ctx.densities()
+    t, s = ctx.time()
+    obs = ctx.observables()
+    ctx.close()
+    ev = oracle.Evolver(w.lattice, w.functional, psi)
+    ev.step(w.dt, nsteps)
+    return got, n, k, t, s, obs, ev
+
+
+def test_config1_full_100_steps(lise):
+    """8^3, M = 1024, FP64, 3 start-up + 100 ABM steps: psi and densities within 1e-11."""
+    w = wl.config1()
+    say(f"step {w.name} 100 steps")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 100)
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e_psi, e_n, e_k = rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0)
+    say(f"  rel L2: psi {e_psi:.3e} n {e_n:.3e} kappa {e_k:.3e}")
+    assert abs(t - ev.t) < 1e-13 and s == 103
+    assert e_psi < 1e-11 and e_n < 1e-11 and e_k < 1e-11
+    o = oracle.observables(ev.y, w.lattice, w.functional, ev.t)
+    for key in ("N", "E", "E_kin", "E_int", "E_pair", "mean_abs_delta"):
+        assert abs(obs[key] - o[key]) < 1e-10 * max(1.0, abs(o[key])), key
+    assert np.allclose(obs["r_cm"], o["r_cm"], atol=1e-10)
+
+
+def test_config2_reduced_with_bump(lise):
+    """32^3 lowest-|k| BCS + ramped Gaussian well, M = 32, 12 ABM steps."""
+    w = wl.config2(M=32)
+    say(f"step {w.name} 12 steps (chunked, jgroup 5)")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 12, tuning={"chunk_qpwf": 12, "jgroup": 5})
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e = (rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0))
+    say(f"  rel L2: {e}")
+    assert max(e) < 1e-11
+    o = oracle.observables(ev.y, w.lattice, w.functional, ev.t)
+    assert abs(obs["E_ext"] - o["E_ext"]) < 1e-10 * abs(o["E_ext"])
+    assert abs(obs["E"] - o["E"]) < 1e-10 * abs(o["E"])
+
+
+def test_four_component_step(lise):
+    """C = 4 spin-imbalanced set on 8^3 (FP64), 20 ABM steps."""
+    w = wl.config4(M=48, n=8, precision=wl.FP64)
+    say(f"step {w.name} 20 steps")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 20)
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e = (rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0))
+    say(f"  rel L2: {e}")
+    assert max(e) < 1e-11
+
+
+def test_vortex_fp64_reduced(lise):
+    """Config-3 recipe (vortex line, phase noise) at 16^3, M = 64, FP64, 20 steps."""
+    w = wl.config3(M=64, n=16, precision=wl.FP64)
+    say(f"step {w.name} 20 steps")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 20)
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e = (rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0))
+    say(f"  rel L2: {e}")
+    assert max(e) < 1e-11
+
+
+def test_fp32_density_error_config1(lise):
+    """FP32 bulk with FP64 sums: densities within 1e-5 relative L2 of the FP64 oracle after 100 steps."""
+    w = wl.config1()
+    w.functional.precision = wl.FP32
+    say(f"step {w.name} FP32 100 steps")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 100)
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e = (rel_l2(n, n0), rel_l2(k, k0))
+    say(f"  FP32 density rel L2 {e}, psi {rel_l2(got, ev.y):.3e}")
+    assert max(e) < 1e-5
+
+
+def test_fp32_density_error_vortex(lise):
+    w = wl.config3(M=64, n=24, precision=wl.FP32)
+    say(f"step {w.name} FP32 30 steps")
+    got, n, k, t, s, obs, ev = run_pair(lise, w, 30)
+    n0, k0 = oracle.densities(ev.y, w.functional)
+    e = (rel_l2(n, n0), rel_l2(k, k0))
+    say(f"  FP32 density rel L2 {e}")
+    assert max(e) < 1e-5
+
+
+def test_frozen_uniform_bcs_closed_form(lise):
+    """Frozen U0, Delta0: each momentum evolves by the closed-form 2x2 rotation."""
+    import math
+    lat = wl.Lattice(8, 8, 8, 1.0)
+    U0, D0, mu = 0.15, 0.4 * np.exp(-0.3j), 0.7
+    fn = wl.Functional(ncomp=2, mu_up=mu, mu_dn=mu, frozen=1, U0=U0, Delta0=D0, g=1.0)
+    M = 40
+    idx = wl.k_order(lat)[:M]
+    pw = wl.plane_waves(lat, idx)
+    rng = np.random.default_rng(11)
+    ab = rng.standard_normal((M, 2)) + 1j * rng.standard_normal((M, 2))
+    ab /= np.linalg.norm(ab, axis=1, keepdims=True)
+    psi = ab[:, :, None, None, None] * pw[:, None]
+    say("frozen uniform BCS 8^3 M=40, 200 steps")
+    ctx = lise.Context(lat, M, fn)
+    ctx.set_qpwf(0, psi)
+    dt = 0.004
+    ctx.step(dt, 200)
+    got = ctx.get_qpwf(0, M)
+    t, _ = ctx.time()
+    ctx.close()
+    k2 = np.sum(wl.k_of(lat, idx) ** 2, axis=1)
+    for j in range(M):
+        xi = 0.5 * k2[j] + U0 - mu
+        Hk = np.array([[xi, D0], [np.conj(D0), -xi]])
+        E = math.sqrt(xi * xi + abs(D0) ** 2)
+        exact = (math.cos(E * t) * np.eye(2) - 1j * math.sin(E * t) * Hk / E) @ ab[j]
+        assert np.max(np.abs(got[j] / pw[j][None] - exact[:, None, None, None])) < 2e-9
+
+
+def test_free_plane_wave_phase(lise):
+    lat = wl.Lattice(16, 16, 16, 1.0)
+    fn = wl.Functional(ncomp=2, mu_up=0.0, mu_dn=0.0, beta=0.37, g=1.5, w=2.0)
+    idx = np.array([[0, 0, 0], [1, 0, 0], [3, -5, 2], [-8, -8, -8], [7, 7, -8]])
+    pw = wl.plane_waves(lat, idx)
+    psi = np.zeros((len(idx), 2, 16, 16, 16), dtype=complex)
+    psi[:, 0] = pw
+    say("free plane waves 16^3, 60 steps")
+    ctx = lise.Context(lat, len(idx), fn)
+    ctx.set_qpwf(0, psi)
+    dt = 0.002
+    ctx.step(dt, 60)
+    got = ctx.get_qpwf(0, len(idx))
+    ctx.close()
+    ev = oracle.Evolver(lat, fn, psi)
+    ev.step(dt, 60)
+    assert rel_max(got, ev.y) < 1e-12
+    k2 = np.sum(wl.k_of(lat, idx) ** 2, axis=1)
+    t = 63 * dt
+    for j in range(len(idx)):
+        ph = np.exp(-0.5j * k2[j] * t)
+        z = 0.5 * k2[j] * dt
+        bound = 2 * (3 * z ** 5 / 120 + 60 * 2e-9 * (z / 0.074) ** 6) + 1e-12
+        assert np.max(np.abs(got[j, 0] - ph * pw[j])) < bound * np.max(np.abs(pw[j]))
+        assert np.max(np.abs(got[j, 1])) == 0.0
+
+
+def test_single_qpwf_and_odd_lattice(lise):
+    lat = wl.Lattice(5, 3, 4, 1.0)
+    fn = wl.Functional(ncomp=2, mu_up=0.3, mu_dn=0.3, beta=0.37, g=1.0, w=2.0)
+    psi = random_state(lat, 1, 2, seed=3)
+    say("M=1 on 5x3x4, 10 steps")
+    ctx = lise.Context(lat, 1, fn)
+    ctx.set_qpwf(0, psi)
+    ctx.step(0.01, 10)
+    got = ctx.get_qpwf(0, 1)
+    ctx.close()
+    ev = oracle.Evolver(lat, fn, psi)
+    ev.step(0.01, 10)
+    assert rel_l2(got, ev.y) < 1e-12
+
+
+def test_deterministic_repeats(lise):
+    w = wl.config2(M=24, n=16, steps=10)
+    psi = w.qpwfs()
+    outs = []
+    for _ in range(2):
+        say("determinism 16^3 M=24, 8 steps")
+        ctx = lise.Context(w.lattice, w.M, w.functional)
+        ctx.set_tuning(chunk_qpwf=10, jgroup=4)
+        ctx.set_qpwf(0, psi)
+        ctx.step(w.dt, 8)
+        outs.append((ctx.get_qpwf(0, w.M), ctx.densities()[0]))
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_time_reversal(lise):
+    w = wl.config1(M=128)
+    psi = w.qpwfs()
+    say("time reversal 8^3 M=128: 40 forward, 40 backward")
+    ctx = lise.Context(w.lattice, w.M, w.functional)
+    ctx.set_qpwf(0, psi)
+    ctx.step(0.004, 40)
+    ctx.step(-0.004, 40)
+    got = ctx.get_qpwf(0, w.M)
+    t, _ = ctx.time()
+    ctx.close()
+    assert abs(t) < 1e-13
+    assert rel_max(got, psi) < 1e-6
+
+
+def test_error_paths(lise):
+    lat = wl.Lattice(8, 8, 8, 1.0)
+    fn = wl.Functional(ncomp=2)
+    ctx = lise.Context(lat, 4, fn)
+    with pytest.raises(lise.LiseError, match="STATE"):
+        ctx.step(0.01, 1)            # qpwfs not set
+    with pytest.raises(lise.LiseError, match="ARG"):
+        ctx.set_qpwf(3, np.zeros((2, 2, 8, 8, 8), dtype=complex))
+    with pytest.raises(lise.LiseError, match="ARG"):
+        ctx.step(0.0, 1)
+    ctx.set_qpwf(0, random_state(lat, 4, 2, 1) * np.nan)
+    with pytest.raises(lise.LiseError, match="NAN"):
+        ctx.step(0.01, 1)
+    ctx.close()
