@@ -1,0 +1,220 @@
+"""Benchmark of the TDSLDA time step on one MI355X.
+
+Default workload: 32^3 periodic lattice, 8192 two-component qpwfs (the
+lowest-|k| BCS states, Delta0 = 0.3, mu = 0.5, g = 2, beta = 0.37) with a
+ramped Gaussian external well, FP64, dt = 0.002.  A "step" is one
+Adams-Bashforth-Milne step of all qpwfs (two Hamiltonian applications, two
+density rebuilds).  Inputs are generated on the host, uploaded, and the
+series-expansion start-up plus the warm-up steps run before the timed region.
+
+Prints one JSON line: qpwf-steps/s of the whole job, the roofline of the
+dominant kernel (the plane kernel of the ABM phases, timed with HIP events
+inside the library on its stream), and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12           # MI355X HBM3E, bytes/s
+METRIC = "qpwf-steps/sec + % HBM roofline, FP32/batched vs FP64 at stated density error"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name, M=None):
+    import workloads as wl
+    if name == "cfg2":
+        return wl.config2(M=M)
+    if name == "cfg2_fp32":
+        w = wl.config2(M=M)
+        w.functional.precision = wl.FP32
+        w.name = w.name.replace("fp64", "fp32")
+        return w
+    if name == "cfg1":
+        return wl.config1(M=M)
+    raise ValueError(name)
+
+
+def upload(ctx, w, piece=512):
+    for j0 in range(0, w.M, piece):
+        k = min(piece, w.M - j0)
+        ctx.set_qpwf(j0, np.ascontiguousarray(w.qpwfs(j0, k)))
+
+
+def run_gpu(w, steps, warmup, tuning=None, profile=True):
+    import torch
+    import paper_2009_00745_amd as lise
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = lise.Context(w.lattice, w.M, w.functional, stream=stream)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    t0 = time.time()
+    upload(ctx, w)
+    log(f"{w.name}: uploaded {w.M} qpwfs in {time.time() - t0:.1f}s, device memory {ctx.memory() / 2**30:.1f} GiB")
+    ctx.startup(w.dt)
+    if warmup:
+        ctx.step(w.dt, warmup)
+    torch.cuda.synchronize()
+    log(f"{w.name}: start-up + {warmup} warm-up steps done")
+    if profile:
+        ctx.profile(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.step(w.dt, steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = {}
+    if profile:
+        for cls, name in ((0, "plane"), (1, "zaxis"), (2, "fields")):
+            prof[name] = ctx.profile_read(cls)
+        ctx.profile(0)
+    log(f"{w.name}: {steps} steps in {t2 - t1:.3f}s")
+    return ctx, t2 - t1, prof
+
+
+def cpu_baseline(w_name, M_sample, steps):
+    """The oracle, unchanged, on M_sample qpwfs of the same workload."""
+    import oracle
+    w = make_workload(w_name, M=M_sample)
+    psi = w.qpwfs()
+    ev = oracle.Evolver(w.lattice, w.functional, psi)
+    ev.startup(w.dt)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev.abm_step()
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": M_sample * steps / dt, "unit": "qpwf-steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{w.name}: {M_sample} of the workload's qpwfs on the same lattice, "
+                      f"{steps} ABM steps after the start-up ({dt:.1f}s); oracle cost is linear "
+                      f"in qpwfs; densities summed over the sample only; CPU {cpu}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--M", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--jgroup", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path is built and measured on a single MI355X; "
+              "multi-GPU sharding over qpwfs is a design note, not a run (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    import paper_2009_00745_amd as lise
+    lise.load_library()
+
+    w = make_workload(args.workload, M=args.M)
+    tuning = {}
+    if args.chunk or args.jgroup:
+        tuning = {"chunk_qpwf": args.chunk, "jgroup": args.jgroup}
+    C, N = w.functional.ncomp, w.lattice.n
+    esz = 16 if w.functional.precision == 0 else 8
+    ctx, elapsed, prof = run_gpu(w, args.steps, args.warmup, tuning)
+    value = w.M * args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    b_alg = 16 * C * N * esz                      # compulsory state bytes per qpwf-step
+    n_plane, ms_plane = prof["plane"]
+    # the plane kernel moves the ABM state: phase 1 reads 6 and writes 1 state array,
+    # phase 2 reads 7 and writes 2, per qpwf (the split of the 16-array step minimum)
+    alg_bytes_total = args.steps * w.M * b_alg
+    avg_launch_s = ms_plane / n_plane / 1e3
+    achieved = (alg_bytes_total / n_plane) / avg_launch_s
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "kernel": "kp_kernel (ABM phases)", "launches": n_plane,
+                "avg_launch_ms": ms_plane / n_plane,
+                "alg_bytes_per_launch": alg_bytes_total / n_plane}
+    breakdown = {k: {"launches": n, "ms_per_step": ms / args.steps} for k, (n, ms) in prof.items()}
+    t_now, s_now = ctx.time()
+    n64, k64 = ctx.densities()
+    obs = ctx.observables()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
+    variants = {}
+    if not args.no_fp32 and args.workload == "cfg2":
+        w32 = make_workload("cfg2_fp32", M=args.M)
+        ctx32, el32, prof32 = run_gpu(w32, args.steps, args.warmup, tuning)
+        n32, k32 = ctx32.densities()
+        t32, s32 = ctx32.time()
+        ctx32.close()
+        assert s32 == s_now
+        variants["fp32_same_workload"] = {
+            "value": w32.M * args.steps / el32, "unit": "qpwf-steps/s",
+            "ms_per_step": 1e3 * el32 / args.steps,
+            "kernel_ms_per_step": {k: ms / args.steps for k, (n, ms) in prof32.items()},
+            "speedup_vs_fp64": (w32.M * args.steps / el32) / value,
+            "density_rel_l2_vs_fp64": {
+                "n": float(np.linalg.norm(n32 - n64) / np.linalg.norm(n64)),
+                "kappa": float(np.linalg.norm(k32 - k64) / np.linalg.norm(k64))},
+            "after_steps": int(s32),
+            "step_hbm_frac": (w32.M * args.steps / el32) * 16 * C * N * 8 / HBM_PEAK}
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample")
+        cpu = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "qpwf-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.functional.precision == 0 else "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.lattice.nx}^3 lattice, {w.M} two-component qpwfs, "
+                               f"dt={w.dt}, {w.notes}",
+                   "lattice": [w.lattice.nx, w.lattice.ny, w.lattice.nz], "n_qpwf": w.M,
+                   "ncomp": C, "dt": w.dt, "tuning": tuning or "default"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "step_hbm_frac": value * b_alg / HBM_PEAK,
+        "b_alg_per_qpwf_step": b_alg,
+        "kernel_ms_per_step": breakdown,
+        "observables": {"t": t_now, "N": obs["N"], "E": obs["E"], "norm_drift_max": obs["norm_drift_max"]},
+        "variants": variants,
+        "host": platform.node(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,12 +115,15 @@ typedef struct {
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
  *                (sets the number of density partial sums)
  *   fused      : 0 or 1 = whole-cube kernel when the cube fits in LDS,
- *                -1 = never (always the z-axis kernel plus plane kernel) */
+ *                -1 = never (always the z-axis kernel plus plane kernel)
+ *   generic    : 1 = use the runtime-sized LDS FFT kernels even where a
+ *                size-specialised register-FFT kernel exists (sides 8, 16,
+ *                20, 24, 32, 48, 64; square xy-planes for the plane kernel) */
 typedef struct {
     int32_t chunk_qpwf;
     int32_t jgroup;
     int32_t fused;
-    int32_t reserved;
+    int32_t generic;
 } lise_tuning;
 
 /* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the
@@ -189,7 +192,8 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
  * the ABM phases, 1 = z-axis kernel, 2 = density reduction + potentials,
  * 3 = plane kernel outside the ABM phases: start-up, apply-H, energy) the
  * number of launches and their summed duration in milliseconds, and clears
- * the counters of every class. */
+ * that class's counters.  Returns LISE_E_STATE if more than 8192 launches
+ * were recorded since the previous read (the event pool is fixed). */
 int lise_profile(lise_ctx *c, int32_t enable);
 int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 

@@ -13,6 +13,7 @@
 
 #include "lise.h"
 #include "lise_device.hpp"
+#include "lise_fast.hpp"
 
 using namespace lise;
 
@@ -78,6 +79,7 @@ struct Prof {
     std::vector<Rec> recs;
     double total_ms[4] = {0, 0, 0, 0};
     long long count[4] = {0, 0, 0, 0};
+    bool overflow = false;
 };
 
 }  // namespace
@@ -114,9 +116,11 @@ struct lise_ctx {
     AxisPlan px, py, pz;
 
     // tuning
-    int chunk = 0, jg = 16, fused_pref = 1;
+    int chunk = 0, jg = 16, fused_pref = 1, generic = 0;
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
+    bool fast_xy = false, fast_z = false;   // size-specialised register-FFT kernels
+    int tw_full_xy = -1, tw_full_z = -1;    // offsets of W_n^j tables (j < n)
 
     // state
     std::vector<char> set_mask;   // which qpwfs were set (coarse: count)
@@ -164,7 +168,11 @@ cpx<T>* S(lise_ctx* c, int i) { return reinterpret_cast<cpx<T>*>(c->buf[i]); }
 // ---- profiling -------------------------------------------------------------
 void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev) {
     *ev = nullptr;
-    if (!c->prof.on || c->prof.used + 2 > c->prof.pool.size()) return;
+    if (!c->prof.on) return;
+    if (c->prof.used + 2 > c->prof.pool.size()) {
+        c->prof.overflow = true;
+        return;
+    }
     *ev = c->prof.pool[c->prof.used];
     (void)hipEventRecord(*ev, c->stream);
     (void)cls;
@@ -203,6 +211,15 @@ void dfree(void** p) {
 size_t kp_lds_bytes(const lise_ctx* c, int zb) { return 2ull * 2ull * (size_t)zb * c->lat.nx * c->lat.ny * c->esz; }
 size_t kz_lds_bytes(const lise_ctx* c, int yb) { return 2ull * (size_t)c->lat.nz * yb * c->lat.nx * c->esz; }
 
+bool fast_side(int n) {
+    return n == 8 || n == 16 || n == 20 || n == 24 || n == 32 || n == 48 || n == 64;
+}
+
+size_t fast_kp_lds(const lise_ctx* c) {
+    const size_t n = c->lat.nx;
+    return (n + 2 * n * (n + 1)) * c->esz;
+}
+
 // Choose launch geometry and (re)allocate scratch for the current tuning.
 int configure(lise_ctx* c) {
     const int nx = c->lat.nx, ny = c->lat.ny, nz = c->lat.nz;
@@ -228,6 +245,10 @@ int configure(lise_ctx* c) {
         if (kz_lds_bytes(c, yb) > c->lds_limit)
             return fail(c, LISE_E_UNSUPPORTED, "xz-tile does not fit in LDS");
     }
+    c->fast_xy = !c->fused && !c->generic && nx == ny && fast_side(nx) && fast_kp_lds(c) <= c->lds_limit &&
+                 c->tw_full_xy >= 0;
+    c->fast_z = !c->fused && !c->generic && fast_side(nz) && c->tw_full_z >= 0;
+    if (c->fast_xy) c->zb = 1;
     const long long P = (long long)c->zb * nxy;
     const long long ppt = (P + kThreads - 1) / kThreads;
     if (ppt > 16) return fail(c, LISE_E_UNSUPPORTED, "plane stack of %lld points exceeds 16 per thread", P);
@@ -315,10 +336,36 @@ KPArgs<T> kp_base(lise_ctx* c) {
     return a;
 }
 
+template <typename T, int MODE, int NS>
+void launch_kp_fast_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
+    constexpr int block = plane_block<T, NS>();
+    const size_t lds = std::max(kp_fast_lds<T, NS>(), (size_t)block * sizeof(double));
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((kp_fast<T, NS, MODE>), grid, dim3(block), lds, c->stream, a,
+                       reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
+}
+
 template <typename T, int MODE>
 int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     a.j0 = j0;
     a.kcount = k;
+    if (c->fast_xy) {
+        dim3 grid(c->lat.nz, (k + c->jg - 1) / c->jg);
+        hipEvent_t ev;
+        prof_begin(c, cls, &ev);
+        switch (c->lat.nx) {
+            case 8: launch_kp_fast_n<T, MODE, 8>(c, a, grid); break;
+            case 16: launch_kp_fast_n<T, MODE, 16>(c, a, grid); break;
+            case 20: launch_kp_fast_n<T, MODE, 20>(c, a, grid); break;
+            case 24: launch_kp_fast_n<T, MODE, 24>(c, a, grid); break;
+            case 32: launch_kp_fast_n<T, MODE, 32>(c, a, grid); break;
+            case 48: launch_kp_fast_n<T, MODE, 48>(c, a, grid); break;
+            default: launch_kp_fast_n<T, MODE, 64>(c, a, grid); break;
+        }
+        prof_end(c, cls, ev);
+        return check_launch(c, "kp_fast");
+    }
     dim3 grid(c->lat.nz / c->zb, (k + c->jg - 1) / c->jg);
     // the kinetic-energy mode reuses LDS for a 256-double reduction
     const size_t lds = std::max(kp_lds_bytes(c, c->zb), (size_t)kThreads * sizeof(double));
@@ -337,6 +384,33 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
 
 template <typename T>
 int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k) {
+    if (c->fast_z) {
+        KZFastArgs<T> f;
+        f.nxy = (long long)c->lat.nx * c->lat.ny;
+        f.ncols = (long long)k * c->C * f.nxy;
+        f.j0 = j0;
+        f.C = c->C;
+        const double pi = 3.14159265358979323846;
+        const double lz = c->lat.nz * c->lat.a;
+        f.cz = T(2.0 * pi * pi / (lz * lz) / c->lat.nz);
+        f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
+        f.in = in;
+        f.G = reinterpret_cast<cpx<T>*>(c->G);
+        dim3 grid((unsigned)((f.ncols + kThreads - 1) / kThreads));
+        hipEvent_t ev;
+        prof_begin(c, 1, &ev);
+        switch (c->lat.nz) {
+            case 8: hipLaunchKernelGGL((kz_fast<T, 8>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 16: hipLaunchKernelGGL((kz_fast<T, 16>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 20: hipLaunchKernelGGL((kz_fast<T, 20>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 24: hipLaunchKernelGGL((kz_fast<T, 24>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 32: hipLaunchKernelGGL((kz_fast<T, 32>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 48: hipLaunchKernelGGL((kz_fast<T, 48>), grid, dim3(kThreads), 0, c->stream, f); break;
+            default: hipLaunchKernelGGL((kz_fast<T, 64>), grid, dim3(kThreads), 0, c->stream, f); break;
+        }
+        prof_end(c, 1, ev);
+        return check_launch(c, "kz_fast");
+    }
     KZArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     a.nx = c->lat.nx;
@@ -597,7 +671,7 @@ int kinetic_energy_t(lise_ctx* c, double* ekin) {
     a.D = c->D_cur;
     a.in = ycur<T>(c);
     a.G = reinterpret_cast<const cpx<T>*>(c->G);
-    const long long nwg_per = (long long)(c->lat.nz / c->zb) * ((c->chunk + c->jg - 1) / c->jg);
+    const long long nwg_per = (long long)(c->lat.nz / c->zb) * ((c->chunk + c->jg - 1) / c->jg);  // zb = 1 on the fast path
     if (c->red_cap < nwg_per) {
         dfree(reinterpret_cast<void**>(&c->red));
         CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)std::max<long long>(nwg_per, 4096) * sizeof(double)));
@@ -727,6 +801,20 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     std::vector<cpx<double>> tw;
     if (!make_plan(lat->nx, &c->px, &tw) || !make_plan(lat->ny, &c->py, &tw) || !make_plan(lat->nz, &c->pz, &tw))
         return bail(fail(c, LISE_E_UNSUPPORTED, "no FFT plan"));
+    // W_n^j tables (j < n) for the register-FFT kernels
+    auto full_table = [&](int n) {
+        const int off = (int)tw.size();
+        for (int j = 0; j < n; ++j) {
+            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+            cpx<double> w;
+            w.re = (double)cosl(ang);
+            w.im = (double)sinl(ang);
+            tw.push_back(w);
+        }
+        return off;
+    };
+    if (lat->nx == lat->ny && fast_side(lat->nx)) c->tw_full_xy = full_table(lat->nx);
+    if (fast_side(lat->nz)) c->tw_full_z = full_table(lat->nz);
     if (c->prec == LISE_FP64) {
         int rc = dalloc(c, &c->tw, tw.size() * sizeof(cpx<double>));
         if (rc) return bail(rc);
@@ -922,6 +1010,7 @@ int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     c->chunk = t->chunk_qpwf;
     if (t->jgroup > 0) c->jg = t->jgroup;
     c->fused_pref = (t->fused < 0) ? 0 : 1;
+    c->generic = t->generic ? 1 : 0;
     return configure(c);
 }
 
@@ -948,9 +1037,11 @@ int lise_profile_read(lise_ctx* c, int32_t which, int64_t* launches, double* tot
     c->prof.used = 0;
     if (launches) *launches = c->prof.count[which];
     if (total_ms) *total_ms = c->prof.total_ms[which];
-    for (int k = 0; k < 4; ++k) {
-        c->prof.total_ms[k] = 0.0;
-        c->prof.count[k] = 0;
+    c->prof.total_ms[which] = 0.0;
+    c->prof.count[which] = 0;
+    if (c->prof.overflow) {
+        c->prof.overflow = false;
+        return fail(c, LISE_E_STATE, "profiling event pool exhausted: read the counters more often");
     }
     return LISE_OK;
 }

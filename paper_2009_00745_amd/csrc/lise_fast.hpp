@@ -1,0 +1,480 @@
+// Size-specialised kernels of the TDSLDA step for the lattice sides that
+// occur in practice (8, 16, 20, 24, 32, 48, 64): the FFTs run in registers.
+//
+// z axis (kz_fast): one thread per z-column holds the whole column (N
+//   values) and does forward FFT, the kz^2/2 multiply and the inverse FFT in
+//   registers; consecutive lanes take consecutive x, so every load and store
+//   of a wave is one contiguous run.
+//
+// xy planes (kp_fast): an N-point line is split over L lanes (4, 8 or 16),
+//   lane s holding elements s + L q (q < P = N/L).  Forward transform:
+//     A_s[k1] = DFT_P over q of x[s + L q]          (registers)
+//     B_s[k1] = A_s[k1] * W_N^{s k1}                 (per-lane twiddle)
+//     X[k1 + P k2] = DFT_L over s of B_s[k1]        (radix-2 exchanges across
+//                                                    lanes: DPP, ds_swizzle)
+//   after which lane s holds X[k1 + P bitrev(s)].  The inverse
+//   runs the same steps backwards, so frequency order never has to be
+//   restored.  Rows are transformed first, one LDS transpose gives columns,
+//   the k^2 multiply sits between the forward and inverse column transforms,
+//   and a second transpose returns rows for the inverse x transform, whose
+//   output feeds the local mixing and ABM epilogue straight from registers.
+#pragma once
+
+#include "lise_device.hpp"
+
+namespace lise {
+
+// ---------------------------------------------------------------------------
+// compile-time radix plan (same rule as the host planner)
+struct RadixList {
+    int cnt;
+    int r[8];
+};
+
+constexpr RadixList radix_list(int N) {
+    RadixList L{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    int m = N, e2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++e2;
+    }
+    while (e2 >= 3 && e2 != 4) {
+        L.r[L.cnt++] = 8;
+        e2 -= 3;
+    }
+    if (e2 == 4) {
+        L.r[L.cnt++] = 4;
+        L.r[L.cnt++] = 4;
+        e2 = 0;
+    }
+    if (e2 == 2) L.r[L.cnt++] = 4;
+    if (e2 == 1) L.r[L.cnt++] = 2;
+    while (m % 3 == 0) {
+        L.r[L.cnt++] = 3;
+        m /= 3;
+    }
+    while (m % 5 == 0) {
+        L.r[L.cnt++] = 5;
+        m /= 5;
+    }
+    return L;
+}
+
+constexpr int radix_prod(int N, int S) {
+    RadixList L = radix_list(N);
+    int p = 1;
+    for (int i = 0; i < S; ++i) p *= L.r[i];
+    return p;
+}
+
+// Register Stockham FFT of size N.  tab holds W_TN^j = exp(-2 pi i j/TN)
+// with TN = N * TS, so W_N^j = tab[j * TS].
+template <typename T, int N, int TS, bool INV, int S = 0>
+struct RegFft {
+    static __device__ __forceinline__ void run(cpx<T>* x, const cpx<T>* __restrict__ tab) {
+        constexpr RadixList L = radix_list(N);
+        if constexpr (S < L.cnt) {
+            constexpr int R = L.r[S];
+            constexpr int p = radix_prod(N, S);
+            constexpr int m = N / R;
+            cpx<T> y[N];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                const int k = i % p;
+                cpx<T> a[R];
+#pragma unroll
+                for (int q = 0; q < R; ++q) a[q] = x[i + q * m];
+                if (k != 0) {
+#pragma unroll
+                    for (int q = 1; q < R; ++q) {
+                        cpx<T> w = tab[((q * k * (N / (p * R))) % N) * TS];
+                        if (INV) w.im = -w.im;
+                        a[q] = a[q] * w;
+                    }
+                }
+                SmallDft<T, R, INV ? 1 : -1>::run(a);
+                const int j = (i / p) * p * R + k;
+#pragma unroll
+                for (int s = 0; s < R; ++s) y[j + s * p] = a[s];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = y[i];
+            RegFft<T, N, TS, INV, S + 1>::run(x, tab);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Lane exchanges: partner lane s ^ D.  D = 1, 2 use DPP quad_perm
+// ([1,0,3,2] and [2,3,0,1]); D = 4, 8, 16 use ds_swizzle in bit mode
+// (and-mask 0x1f, xor-mask D), which stays inside groups of 32 lanes.
+constexpr int kQuadXor1 = 0xB1;
+constexpr int kQuadXor2 = 0x4E;
+
+template <int D>
+__device__ __forceinline__ int xchg_i(int v) {
+    if constexpr (D == 1) return __builtin_amdgcn_mov_dpp(v, kQuadXor1, 0xF, 0xF, false);
+    else if constexpr (D == 2) return __builtin_amdgcn_mov_dpp(v, kQuadXor2, 0xF, 0xF, false);
+    else return __builtin_amdgcn_ds_swizzle(v, 0x1F | (D << 10));
+}
+template <int D>
+__device__ __forceinline__ float xchg(float v) { return __int_as_float(xchg_i<D>(__float_as_int(v))); }
+template <int D>
+__device__ __forceinline__ double xchg(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = xchg_i<D>((int)(b & 0xffffffffLL));
+    const int hi = xchg_i<D>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int D, typename T>
+__device__ __forceinline__ cpx<T> xchg(cpx<T> v) {
+    return mk(xchg<D>(v.re), xchg<D>(v.im));
+}
+
+__host__ __device__ constexpr int bitrev(int s, int L) {
+    int r = 0;
+    for (int b = 1; b < L; b <<= 1) r = (r << 1) | ((s & b) ? 1 : 0);
+    return r;
+}
+
+// Radix-2 decimation-in-frequency stages across lanes, partner distance D
+// down to 1.  tab holds W_N^j; W_{2D}^j = tab[j N / (2D)].
+template <typename T, int P, int L, int D>
+struct LaneDif {
+    static __device__ __forceinline__ void run(cpx<T>* x, const cpx<T>* __restrict__ tab, int s) {
+        if constexpr (D >= 1) {
+            constexpr int N = L * P;
+            const bool up = (s & D) != 0;
+            cpx<T> w = mk(T(1), T(0));
+            if constexpr (D > 1) w = tab[(s & (D - 1)) * (N / (2 * D))];
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) {
+                const cpx<T> p = xchg<D>(x[k1]);
+                cpx<T> d = p - x[k1];
+                if constexpr (D > 1) d = d * w;
+                x[k1] = up ? d : x[k1] + p;
+            }
+            LaneDif<T, P, L, D / 2>::run(x, tab, s);
+        }
+    }
+};
+
+// Radix-2 decimation-in-time stages across lanes (inverse transform), partner
+// distance D up to L/2; the upper element is twiddled by W_{2D}^{-j} first.
+template <typename T, int P, int L, int D>
+struct LaneDit {
+    static __device__ __forceinline__ void run(cpx<T>* x, const cpx<T>* __restrict__ tab, int s) {
+        if constexpr (D < L) {
+            constexpr int N = L * P;
+            const bool up = (s & D) != 0;
+            cpx<T> w = mk(T(1), T(0));
+            if constexpr (D > 1) w = conjg(tab[(s & (D - 1)) * (N / (2 * D))]);
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) {
+                cpx<T> v = x[k1];
+                if constexpr (D > 1) v = up ? v * w : v;
+                const cpx<T> p = xchg<D>(v);
+                x[k1] = up ? p - v : v + p;
+            }
+            LaneDit<T, P, L, 2 * D>::run(x, tab, s);
+        }
+    }
+};
+
+// Forward line transform of N = L*P points over L lanes: x[q] = element
+// s + L q on entry, X[k1 + P bitrev(s)] at x[k1] on exit.
+template <typename T, int P, int L>
+__device__ __forceinline__ void lane_fwd(cpx<T>* x, const cpx<T>* __restrict__ tab, int s) {
+    RegFft<T, P, L, false>::run(x, tab);
+#pragma unroll
+    for (int k1 = 1; k1 < P; ++k1) x[k1] = x[k1] * tab[s * k1];
+    LaneDif<T, P, L, L / 2>::run(x, tab, s);
+}
+
+// Inverse of lane_fwd, unnormalised: N * element s + L q at x[q] on exit.
+template <typename T, int P, int L>
+__device__ __forceinline__ void lane_inv(cpx<T>* x, const cpx<T>* __restrict__ tab, int s) {
+    LaneDit<T, P, L, 1>::run(x, tab, s);
+#pragma unroll
+    for (int k1 = 1; k1 < P; ++k1) x[k1] = x[k1] * conjg(tab[s * k1]);
+    RegFft<T, P, L, true>::run(x, tab);
+}
+
+// lanes per line of the plane kernel: enough that a lane holds at most 4
+// points of a line, capped at 16
+template <typename T, int N>
+constexpr int plane_lanes() {
+    constexpr int maxp = 4;
+    int L = 4;
+    while (N / L > maxp && L < 16 && N % (2 * L) == 0) L *= 2;
+    return L;
+}
+
+template <typename T, int N>
+constexpr int plane_block() {
+    constexpr int t = plane_lanes<T, N>() * N;
+    return (t + 63) / 64 * 64;
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue of one point shared by the plane kernels: local mixing of
+// Eq. (tdslda) and the mode's update, plus density accumulation.
+
+template <typename T, int MODE>
+__device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
+                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt,
+                                               double& dn, double& dkr, double& dki, double& ekin) {
+    if (MODE == KP_KINETIC) {
+        ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
+        return;
+    }
+    const T sg = T(a.sgn[pr]);
+    const T Vr = T(a.V[rpt]);
+    const cpx<T> Dl = mk(T(sg * T(a.D[2 * rpt])), T(sg * T(a.D[2 * rpt + 1])));
+    const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
+    const cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
+    const cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
+    cpx<T> va, vb;
+    if (MODE == KP_APPLY) {
+        const cpx<T> oa = coef * Ha, ob = coef * Hb;
+        if (a.deriv) {
+            a.deriv[ea] = mk(Ha.im, -Ha.re);
+            a.deriv[eb] = mk(Hb.im, -Hb.re);
+        }
+        va = oa;
+        vb = ob;
+        if (a.acc) {
+            const cpx<T> pa = a.acc_from_in ? fa : a.acc[ea];
+            const cpx<T> pb = a.acc_from_in ? fb : a.acc[eb];
+            va = pa + oa;
+            vb = pb + ob;
+            a.acc[ea] = va;
+            a.acc[eb] = vb;
+        }
+        if (a.out) {
+            a.out[ea] = oa;
+            a.out[eb] = ob;
+        }
+    } else if (MODE == KP_ABM1) {
+        const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);
+        const cpx<T> pa = T(0.5) * (fa + a.a1[ea]) +
+                          cdt * (T(119) * da - T(99) * a.a2[ea] + T(69) * a.a3[ea] - T(17) * a.a4[ea]);
+        const cpx<T> pb = T(0.5) * (fb + a.a1[eb]) +
+                          cdt * (T(119) * db - T(99) * a.a2[eb] + T(69) * a.a3[eb] - T(17) * a.a4[eb]);
+        va = pa - T(161.0 / 170.0) * a.a5[ea];
+        vb = pb - T(161.0 / 170.0) * a.a5[eb];
+        a.a6[ea] = da;
+        a.a6[eb] = db;
+        a.a4[ea] = va;
+        a.a4[eb] = vb;
+    } else {
+        const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);
+        const cpx<T> dna = a.a1[ea], dnb = a.a1[eb];
+        const cpx<T> pa = fa + T(161.0 / 170.0) * dna;
+        const cpx<T> pb = fb + T(161.0 / 170.0) * dnb;
+        const cpx<T> cA = T(0.5) * (a.a2[ea] + a.a3[ea]) +
+                          cdt * (T(17) * ma + T(51) * a.a4[ea] + T(3) * a.a5[ea] + a.a6[ea]);
+        const cpx<T> cB = T(0.5) * (a.a2[eb] + a.a3[eb]) +
+                          cdt * (T(17) * mb + T(51) * a.a4[eb] + T(3) * a.a5[eb] + a.a6[eb]);
+        const cpx<T> dA = pa - cA, dB = pb - cB;
+        va = cA + T(9.0 / 170.0) * dA;
+        vb = cB + T(9.0 / 170.0) * dB;
+        a.a1[ea] = dA;
+        a.a1[eb] = dB;
+        a.a3[ea] = va;
+        a.a3[eb] = vb;
+    }
+    if (a.dens_src) {
+        const double br = double(vb.re), bi = double(vb.im);
+        const double ar = double(va.re), ai = double(va.im);
+        dn += a.w * (br * br + bi * bi);
+        const double hs = 0.5 * a.w * double(a.sgn[pr]);
+        dkr += hs * (br * ar + bi * ai);
+        dki += hs * (br * ai - bi * ar);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z axis: one thread per column, the column in registers.
+
+template <typename T>
+struct KZFastArgs {
+    long long ncols;     // K * C * nx * ny columns in this launch
+    long long nxy;
+    long long j0;
+    int C;
+    T cz;                // (2 pi^2 / L_z^2) / nz
+    const cpx<T>* tw;    // W_nz^j, j < nz
+    const cpx<T>* in;
+    cpx<T>* G;
+};
+
+template <typename T, int NZ>
+__global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
+    __shared__ cpx<T> tab[NZ];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    __syncthreads();
+    const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= a.ncols) return;
+    const long long jc = col / a.nxy, r = col - jc * a.nxy;
+    const cpx<T>* src = a.in + (a.j0 * a.C + jc) * NZ * a.nxy + r;
+    cpx<T>* dst = a.G + jc * NZ * a.nxy + r;
+    cpx<T> x[NZ];
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) x[z] = src[z * a.nxy];
+    RegFft<T, NZ, 1, false>::run(x, tab);
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+        const int m = (2 * z < NZ) ? z : z - NZ;
+        x[z] = (a.cz * T(m * m)) * x[z];
+    }
+    RegFft<T, NZ, 1, true>::run(x, tab);
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) dst[z * a.nxy] = x[z];
+}
+
+// ---------------------------------------------------------------------------
+// xy planes of a square lattice side N; one workgroup per z-plane and qpwf
+// group, 4N active threads (row = tid/4, lane s = tid%4).
+
+template <typename T, int N>
+constexpr size_t kp_fast_lds() {
+    return (size_t)(N + 2 * N * (N + 1)) * sizeof(cpx<T>);
+}
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((plane_block<T, N>())) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
+    constexpr int L = plane_lanes<T, N>();
+    constexpr int P = N / L;
+    constexpr int LD = N + 1;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* La = tab + N;
+    cpx<T>* Lb = La + N * LD;
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (int i = tid; i < N; i += nth) tab[i] = twN[i];
+    const bool act = tid < L * N;
+    const int row = tid / L;
+    const int s = tid % L;
+    const int brs = bitrev(s, L);
+    const int z = blockIdx.x;
+    constexpr long long nxy = (long long)N * N;
+    const long long N3 = nxy * a.nz;
+    const int jbeg = blockIdx.y * a.jg;
+    const int jend = min(a.kcount, jbeg + a.jg);
+    const T cdt = T(a.dt / 48.0);
+    const cpx<T> coef = mk(T(a.coef_re), T(a.coef_im));
+    double dn[P], dkr[P], dki[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
+    double ekin = 0.0;
+    __syncthreads();
+
+    for (int jl = jbeg; jl < jend; ++jl) {
+        const long long jgl = a.j0 + jl;
+        for (int pr = 0; pr < a.npair; ++pr) {
+            const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
+            const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
+            cpx<T> xa[P], xb[P];
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    xa[q] = a.in[offa + row * N + s + L * q];
+                    xb[q] = a.in[offb + row * N + s + L * q];
+                }
+                lane_fwd<T, P, L>(xa, tab, s);
+                lane_fwd<T, P, L>(xb, tab, s);
+#pragma unroll
+                for (int k1 = 0; k1 < P; ++k1) {
+                    La[(k1 + P * brs) * LD + row] = xa[k1];
+                    Lb[(k1 + P * brs) * LD + row] = xb[k1];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const int col = row;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    xa[q] = La[col * LD + s + L * q];
+                    xb[q] = Lb[col * LD + s + L * q];
+                }
+                lane_fwd<T, P, L>(xa, tab, s);
+                lane_fwd<T, P, L>(xb, tab, s);
+                const int mx = (2 * col < N) ? col : col - N;
+                const T fx = a.cx * T(mx * mx);
+#pragma unroll
+                for (int k1 = 0; k1 < P; ++k1) {
+                    const int ky = k1 + P * brs;
+                    const int my = (2 * ky < N) ? ky : ky - N;
+                    const T f = fx + a.cy * T(my * my);
+                    xa[k1] = f * xa[k1];
+                    xb[k1] = f * xb[k1];
+                }
+                lane_inv<T, P, L>(xa, tab, s);
+                lane_inv<T, P, L>(xb, tab, s);
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    La[col * LD + s + L * q] = xa[q];
+                    Lb[col * LD + s + L * q] = xb[q];
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int k1 = 0; k1 < P; ++k1) {
+                    xa[k1] = La[(k1 + P * brs) * LD + row];
+                    xb[k1] = Lb[(k1 + P * brs) * LD + row];
+                }
+                lane_inv<T, P, L>(xa, tab, s);
+                lane_inv<T, P, L>(xb, tab, s);
+                const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z) * nxy;
+                const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z) * nxy;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int pt = row * N + s + L * q;
+                    cpx<T> Ta = xa[q], Tb = xb[q];
+                    if (!a.fused) {
+                        Ta = Ta + a.G[lofa + pt];
+                        Tb = Tb + a.G[lofb + pt];
+                    }
+                    const long long ea = offa + pt, eb = offb + pt;
+                    point_epilogue<T, MODE>(a, pr, Ta, Tb, a.in[ea], a.in[eb], ea, eb, (long long)z * nxy + pt,
+                                            coef, cdt, dn[q], dkr[q], dki[q], ekin);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (MODE == KP_KINETIC) {
+        double* red = reinterpret_cast<double*>(smem_raw);
+        red[tid] = ekin;
+        __syncthreads();
+        int st = 1;
+        while (st < nth) st <<= 1;
+        for (st >>= 1; st > 0; st >>= 1) {
+            if (tid < st && tid + st < nth) red[tid] += red[tid + st];
+            __syncthreads();
+        }
+        if (tid == 0) a.epart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        return;
+    }
+    if (a.dens_src && act) {
+        double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int pt = row * N + s + L * q;
+            if (a.accumulate) {
+                base[pt] += dn[q];
+                base[N3 + pt] += dkr[q];
+                base[2 * N3 + pt] += dki[q];
+            } else {
+                base[pt] = dn[q];
+                base[N3 + pt] = dkr[q];
+                base[2 * N3 + pt] = dki[q];
+            }
+        }
+    }
+}
+
+}  // namespace lise

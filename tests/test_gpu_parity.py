@@ -56,8 +56,15 @@ APPLY_CASES = [
     (20, 20, 20, 1.0, 2, 3, 0, {}),
     (24, 16, 20, 1.0, 4, 2, 0, {}),
     (32, 32, 32, 1.0, 2, 3, 0, {}),
+    (32, 32, 32, 1.0, 2, 3, 0, {"generic": 1}),
+    (24, 24, 24, 1.0, 4, 2, 0, {}),
+    (20, 20, 16, 1.0, 2, 3, 0, {"chunk_qpwf": 2, "jgroup": 1}),
     (16, 16, 16, 1.0, 2, 6, 1, {}),
+    (16, 16, 16, 1.0, 2, 6, 1, {"fused": -1}),
     (48, 48, 48, 1.0, 2, 2, 1, {}),
+    (48, 48, 48, 1.0, 2, 2, 1, {"generic": 1}),
+    (64, 64, 64, 1.0, 4, 1, 1, {}),
+    (8, 8, 8, 1.0, 2, 4, 0, {"fused": -1, "generic": 0}),
 ]
 
 
