@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,6 +143,16 @@ def main():
     torch.cuda.set_device(0)
     import paper_2009_00745_amd as lise
     lise.load_library()
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
 
     w = make_workload(args.workload, M=args.M)
     tuning = {}

@@ -256,9 +256,10 @@ int configure(lise_ctx* c) {
 
     long long chunk = c->chunk > 0 ? c->chunk : 0;
     if (chunk <= 0) {
-        // default: a z-scratch of ~256 MB (the size of the Infinity Cache)
+        // default: a z-scratch of ~1 GiB; larger launches measured faster than
+        // cache-sized ones (fewer launches, more workgroups in flight)
         const long long per_bytes = c->per * (long long)c->esz;
-        chunk = std::max<long long>(c->jg, (256LL << 20) / std::max<long long>(per_bytes, 1));
+        chunk = std::max<long long>(c->jg, (1LL << 30) / std::max<long long>(per_bytes, 1));
     }
     chunk = std::min<long long>(chunk, c->M);
     chunk = std::max<long long>(chunk, 1);
@@ -565,7 +566,7 @@ int abm_step_t(lise_ctx* c) {
     const int d2 = 2 + (c->dn + 2) % 4;         // y'_{n-2}
     const int d3 = 2 + (c->dn + 1) % 4;         // y'_{n-3}, then m
     const int yn = c->iy, ym1 = 1 - c->iy;
-    // phase 1: H y_n -> y'_n, p, m; densities of m
+    // phase 1: H y_n -> y'_n, m, X, Y; densities of m
     {
         KPArgs<T> a = kp_base<T>(c);
         a.V = c->V_cur;
@@ -583,19 +584,15 @@ int abm_step_t(lise_ctx* c) {
         CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0)));
     }
     CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, c->t + dt));
-    // phase 2: H m -> m', c, y_{n+1}, d_{n+1}; densities of y_{n+1}
+    // phase 2: H m -> m', y_{n+1}, p_{n+1} - c_{n+1}; densities of y_{n+1}
     {
         KPArgs<T> a = kp_base<T>(c);
         a.V = c->V_tmp;
         a.D = c->D_tmp;
-        a.in = S<T>(c, d3);
+        a.in = S<T>(c, d3);                         // m
         a.G = reinterpret_cast<const cpx<T>*>(c->G);
-        a.a1 = S<T>(c, 6);
-        a.a2 = S<T>(c, yn);
-        a.a3 = S<T>(c, ym1);
-        a.a4 = S<T>(c, d0);
-        a.a5 = S<T>(c, d1);
-        a.a6 = S<T>(c, d2);
+        a.a1 = S<T>(c, ym1);                        // Y -> y_{n+1}
+        a.a5 = S<T>(c, 6);                          // X -> p_{n+1} - c_{n+1}
         a.dt = dt;
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0)));

@@ -255,10 +255,9 @@ struct KPArgs {
     cpx<T>* deriv;
     int acc_from_in;
     double coef_re, coef_im;
-    // KP_ABM1: a1 = y_{n-1}, a2 = y'_{n-1}, a3 = y'_{n-2}, a4 = y'_{n-3} -> m,
-    //          a5 = d_n, a6 -> y'_n
-    // KP_ABM2: in = m, a1 = d_n -> d_{n+1}, a2 = y_n, a3 = y_{n-1} -> y_{n+1},
-    //          a4 = y'_n, a5 = y'_{n-1}, a6 = y'_{n-2}
+    // KP_ABM1: in = y_n, a1 = y_{n-1} -> Y, a2 = y'_{n-1}, a3 = y'_{n-2},
+    //          a4 = y'_{n-3} -> m, a5 = p_n - c_n -> X, a6 -> y'_n
+    // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = X -> p_{n+1} - c_{n+1}
     cpx<T>* a1;
     cpx<T>* a2;
     cpx<T>* a3;
@@ -271,6 +270,103 @@ struct KPArgs {
     int accumulate;   // 0: store partials, 1: add to them
     double* epart;    // KP_KINETIC: one float64 per workgroup
 };
+
+// ---------------------------------------------------------------------------
+// Epilogue of one point shared by the plane kernels: local mixing of
+// Eq. (tdslda) with V = U + U_ext and Delta, the mode's update, and the
+// float64 density accumulation of the vector the mode produces.
+//
+// The ABM phases use an exact re-association of Eq. (p), (m), (c), (y) that
+// lets phase 2 read only m, X, Y (and the z-term G):
+//   phase 1: s = (y_n + y_{n-1})/2,
+//            c~ = s + dt/48 (51 y'_n + 3 y'_{n-1} + y'_{n-2})   (c without m'),
+//            Y = p - c~ = dt/48 (68 y'_n - 102 y'_{n-1} + 68 y'_{n-2} - 17 y'_{n-3}),
+//            p = c~ + Y, m = p - 161/170 (p_n - c_n), X = c~ + 9/170 Y;
+//   phase 2: with k = 17 dt / 48 and m' = -i H m,
+//            y_{n+1} = c + 9/170 (p - c) = X + 161/170 k m',
+//            p_{n+1} - c_{n+1} = p - c = Y - k m'.
+// Y is formed from the derivatives directly and X as c~ plus a multiple of Y,
+// so no quantity of the size of y is cancelled and, in float32, the weights
+// of the final combination add up to one exactly.
+// Phase 1 stores y'_n over y'_{n-4}, m over y'_{n-3}, X over p_n - c_n and Y
+// over y_{n-1}; phase 2 stores y_{n+1} over Y and p_{n+1} - c_{n+1} over X.
+
+template <typename T, int MODE>
+__device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
+                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt,
+                                               double& dn, double& dkr, double& dki, double& ekin) {
+    if (MODE == KP_KINETIC) {
+        ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
+        return;
+    }
+    const T sg = T(a.sgn[pr]);
+    const T Vr = T(a.V[rpt]);
+    const cpx<T> Dl = mk(sg * T(a.D[2 * rpt]), sg * T(a.D[2 * rpt + 1]));
+    const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
+    // H u = (h - mu_a) u + s Delta v ;  H v = s Delta^* u - (h - mu_b) v
+    const cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
+    const cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
+    cpx<T> va, vb;   // vector whose densities are accumulated
+    if (MODE == KP_APPLY) {
+        const cpx<T> oa = coef * Ha, ob = coef * Hb;
+        if (a.deriv) {
+            a.deriv[ea] = mk(Ha.im, -Ha.re);
+            a.deriv[eb] = mk(Hb.im, -Hb.re);
+        }
+        va = oa;
+        vb = ob;
+        if (a.acc) {
+            const cpx<T> pa = a.acc_from_in ? fa : a.acc[ea];
+            const cpx<T> pb = a.acc_from_in ? fb : a.acc[eb];
+            va = pa + oa;
+            vb = pb + ob;
+            a.acc[ea] = va;
+            a.acc[eb] = vb;
+        }
+        if (a.out) {
+            a.out[ea] = oa;
+            a.out[eb] = ob;
+        }
+    } else if (MODE == KP_ABM1) {
+        const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);   // y'_n = -i H y_n
+        const cpx<T> sa = T(0.5) * (fa + a.a1[ea]), sb = T(0.5) * (fb + a.a1[eb]);
+        const cpx<T> d1a = a.a2[ea], d1b = a.a2[eb];
+        const cpx<T> d2a = a.a3[ea], d2b = a.a3[eb];
+        const cpx<T> d3a = a.a4[ea], d3b = a.a4[eb];
+        const cpx<T> Ya = cdt * (T(68) * da - T(102) * d1a + T(68) * d2a - T(17) * d3a);
+        const cpx<T> Yb = cdt * (T(68) * db - T(102) * d1b + T(68) * d2b - T(17) * d3b);
+        const cpx<T> ca = sa + cdt * (T(51) * da + T(3) * d1a + d2a);
+        const cpx<T> cb = sb + cdt * (T(51) * db + T(3) * d1b + d2b);
+        va = (ca + Ya) - T(161.0 / 170.0) * a.a5[ea];   // m = p - 161/170 (p_n - c_n)
+        vb = (cb + Yb) - T(161.0 / 170.0) * a.a5[eb];
+        a.a6[ea] = da;
+        a.a6[eb] = db;
+        a.a4[ea] = va;
+        a.a4[eb] = vb;
+        a.a5[ea] = ca + T(9.0 / 170.0) * Ya;
+        a.a5[eb] = cb + T(9.0 / 170.0) * Yb;
+        a.a1[ea] = Ya;
+        a.a1[eb] = Yb;
+    } else {   // KP_ABM2: in = m, a5 = X -> p_{n+1} - c_{n+1}, a1 = Y -> y_{n+1}
+        const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
+        const T k = T(17) * cdt;
+        va = a.a5[ea] + (T(161.0 / 170.0) * k) * ma;
+        vb = a.a5[eb] + (T(161.0 / 170.0) * k) * mb;
+        const cpx<T> ra = a.a1[ea] - k * ma, rb = a.a1[eb] - k * mb;
+        a.a1[ea] = va;
+        a.a1[eb] = vb;
+        a.a5[ea] = ra;
+        a.a5[eb] = rb;
+    }
+    if (a.dens_src) {
+        const double br = double(vb.re), bi = double(vb.im);
+        const double ar = double(va.re), ai = double(va.im);
+        dn += a.w * (br * br + bi * bi);
+        const double hs = 0.5 * a.w * double(a.sgn[pr]);
+        dkr += hs * (br * ar + bi * ai);   // Re(conj(b) a)
+        dki += hs * (br * ai - bi * ar);   // Im(conj(b) a)
+    }
+}
 
 template <typename T, int MODE, int PPT>
 __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
@@ -347,9 +443,6 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
             o = (r == bufA) ? bufB : bufA;
             r = fft_axis<T, true>(r, o, a.px, a.tw, lmx, tid, nth);
 
-            const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
-            const T sg = T(a.sgn[pr]);
-            const long long gofa = offa, gofb = offb;   // element offsets of this plane stack
             const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
             const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
 #pragma unroll
@@ -361,79 +454,8 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
                     Ta = Ta + a.G[lofa + q];
                     Tb = Tb + a.G[lofb + q];
                 }
-                const long long rpt = (long long)z0 * nxy + q;
-                if (MODE == KP_KINETIC) {
-                    ekin += a.w * (double(fb[i].re) * double(Tb.re) + double(fb[i].im) * double(Tb.im));
-                    continue;
-                }
-                const T Vr = T(a.V[rpt]);
-                const cpx<T> Dl = mk(T(sg * a.D[2 * rpt]), T(sg * a.D[2 * rpt + 1]));
-                // H u = (h - mu_a) u + s Delta v ;  H v = s Delta^* u - (h - mu_b) v
-                const cpx<T> Ha = Ta + (Vr - mua) * fa[i] + Dl * fb[i];
-                const cpx<T> Hb = conjg(Dl) * fa[i] - (Tb + (Vr - mub) * fb[i]);
-                const long long ea = gofa + q, eb = gofb + q;
-                cpx<T> va, vb;   // vector whose densities are accumulated
-                if (MODE == KP_APPLY) {
-                    const cpx<T> oa = coef * Ha, ob = coef * Hb;
-                    if (a.deriv) {
-                        a.deriv[ea] = mk(Ha.im, -Ha.re);
-                        a.deriv[eb] = mk(Hb.im, -Hb.re);
-                    }
-                    va = oa;
-                    vb = ob;
-                    if (a.acc) {
-                        const cpx<T> pa = a.acc_from_in ? fa[i] : a.acc[ea];
-                        const cpx<T> pb = a.acc_from_in ? fb[i] : a.acc[eb];
-                        va = pa + oa;
-                        vb = pb + ob;
-                        a.acc[ea] = va;
-                        a.acc[eb] = vb;
-                    }
-                    if (a.out) {
-                        a.out[ea] = oa;
-                        a.out[eb] = ob;
-                    }
-                } else if (MODE == KP_ABM1) {
-                    // y'_n = -i H y_n
-                    const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);
-                    // p = (y_n + y_{n-1})/2 + dt/48 (119 y'_n - 99 y'_{n-1} + 69 y'_{n-2} - 17 y'_{n-3})
-                    // m = p - 161/170 (p_n - c_n)
-                    const cpx<T> pa = T(0.5) * (fa[i] + a.a1[ea]) +
-                                      cdt * (T(119) * da - T(99) * a.a2[ea] + T(69) * a.a3[ea] - T(17) * a.a4[ea]);
-                    const cpx<T> pb = T(0.5) * (fb[i] + a.a1[eb]) +
-                                      cdt * (T(119) * db - T(99) * a.a2[eb] + T(69) * a.a3[eb] - T(17) * a.a4[eb]);
-                    va = pa - T(161.0 / 170.0) * a.a5[ea];
-                    vb = pb - T(161.0 / 170.0) * a.a5[eb];
-                    a.a6[ea] = da;
-                    a.a6[eb] = db;
-                    a.a4[ea] = va;
-                    a.a4[eb] = vb;
-                } else {  // KP_ABM2
-                    const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
-                    const cpx<T> dna = a.a1[ea], dnb = a.a1[eb];
-                    const cpx<T> pa = fa[i] + T(161.0 / 170.0) * dna;              // p = m + 161/170 d_n
-                    const cpx<T> pb = fb[i] + T(161.0 / 170.0) * dnb;
-                    // c = (y_n + y_{n-1})/2 + dt/48 (17 m' + 51 y'_n + 3 y'_{n-1} + y'_{n-2})
-                    const cpx<T> cA = T(0.5) * (a.a2[ea] + a.a3[ea]) +
-                                      cdt * (T(17) * ma + T(51) * a.a4[ea] + T(3) * a.a5[ea] + a.a6[ea]);
-                    const cpx<T> cB = T(0.5) * (a.a2[eb] + a.a3[eb]) +
-                                      cdt * (T(17) * mb + T(51) * a.a4[eb] + T(3) * a.a5[eb] + a.a6[eb]);
-                    const cpx<T> dA = pa - cA, dB = pb - cB;                          // d_{n+1} = p - c
-                    va = cA + T(9.0 / 170.0) * dA;                                    // y_{n+1}
-                    vb = cB + T(9.0 / 170.0) * dB;
-                    a.a1[ea] = dA;
-                    a.a1[eb] = dB;
-                    a.a3[ea] = va;
-                    a.a3[eb] = vb;
-                }
-                if (a.dens_src) {
-                    const double br = double(vb.re), bi = double(vb.im);
-                    const double ar = double(va.re), ai = double(va.im);
-                    dn[i] += a.w * (br * br + bi * bi);
-                    const double hs = 0.5 * a.w * double(a.sgn[pr]);
-                    dkr[i] += hs * (br * ar + bi * ai);   // Re(conj(b) a)
-                    dki[i] += hs * (br * ai - bi * ar);   // Im(conj(b) a)
-                }
+                point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
+                                        (long long)z0 * nxy + q, coef, cdt, dn[i], dkr[i], dki[i], ekin);
             }
             __syncthreads();
         }

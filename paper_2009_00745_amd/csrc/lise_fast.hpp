@@ -217,84 +217,6 @@ constexpr int plane_block() {
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue of one point shared by the plane kernels: local mixing of
-// Eq. (tdslda) and the mode's update, plus density accumulation.
-
-template <typename T, int MODE>
-__device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
-                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt,
-                                               double& dn, double& dkr, double& dki, double& ekin) {
-    if (MODE == KP_KINETIC) {
-        ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
-        return;
-    }
-    const T sg = T(a.sgn[pr]);
-    const T Vr = T(a.V[rpt]);
-    const cpx<T> Dl = mk(T(sg * T(a.D[2 * rpt])), T(sg * T(a.D[2 * rpt + 1])));
-    const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
-    const cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
-    const cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
-    cpx<T> va, vb;
-    if (MODE == KP_APPLY) {
-        const cpx<T> oa = coef * Ha, ob = coef * Hb;
-        if (a.deriv) {
-            a.deriv[ea] = mk(Ha.im, -Ha.re);
-            a.deriv[eb] = mk(Hb.im, -Hb.re);
-        }
-        va = oa;
-        vb = ob;
-        if (a.acc) {
-            const cpx<T> pa = a.acc_from_in ? fa : a.acc[ea];
-            const cpx<T> pb = a.acc_from_in ? fb : a.acc[eb];
-            va = pa + oa;
-            vb = pb + ob;
-            a.acc[ea] = va;
-            a.acc[eb] = vb;
-        }
-        if (a.out) {
-            a.out[ea] = oa;
-            a.out[eb] = ob;
-        }
-    } else if (MODE == KP_ABM1) {
-        const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);
-        const cpx<T> pa = T(0.5) * (fa + a.a1[ea]) +
-                          cdt * (T(119) * da - T(99) * a.a2[ea] + T(69) * a.a3[ea] - T(17) * a.a4[ea]);
-        const cpx<T> pb = T(0.5) * (fb + a.a1[eb]) +
-                          cdt * (T(119) * db - T(99) * a.a2[eb] + T(69) * a.a3[eb] - T(17) * a.a4[eb]);
-        va = pa - T(161.0 / 170.0) * a.a5[ea];
-        vb = pb - T(161.0 / 170.0) * a.a5[eb];
-        a.a6[ea] = da;
-        a.a6[eb] = db;
-        a.a4[ea] = va;
-        a.a4[eb] = vb;
-    } else {
-        const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);
-        const cpx<T> dna = a.a1[ea], dnb = a.a1[eb];
-        const cpx<T> pa = fa + T(161.0 / 170.0) * dna;
-        const cpx<T> pb = fb + T(161.0 / 170.0) * dnb;
-        const cpx<T> cA = T(0.5) * (a.a2[ea] + a.a3[ea]) +
-                          cdt * (T(17) * ma + T(51) * a.a4[ea] + T(3) * a.a5[ea] + a.a6[ea]);
-        const cpx<T> cB = T(0.5) * (a.a2[eb] + a.a3[eb]) +
-                          cdt * (T(17) * mb + T(51) * a.a4[eb] + T(3) * a.a5[eb] + a.a6[eb]);
-        const cpx<T> dA = pa - cA, dB = pb - cB;
-        va = cA + T(9.0 / 170.0) * dA;
-        vb = cB + T(9.0 / 170.0) * dB;
-        a.a1[ea] = dA;
-        a.a1[eb] = dB;
-        a.a3[ea] = va;
-        a.a3[eb] = vb;
-    }
-    if (a.dens_src) {
-        const double br = double(vb.re), bi = double(vb.im);
-        const double ar = double(va.re), ai = double(va.im);
-        dn += a.w * (br * br + bi * bi);
-        const double hs = 0.5 * a.w * double(a.sgn[pr]);
-        dkr += hs * (br * ar + bi * ai);
-        dki += hs * (br * ai - bi * ar);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // z axis: one thread per column, the column in registers.
 
 template <typename T>
@@ -342,8 +264,12 @@ constexpr size_t kp_fast_lds() {
     return (size_t)(N + 2 * N * (N + 1)) * sizeof(cpx<T>);
 }
 
+#ifndef LISE_KP_MIN_WAVES
+#define LISE_KP_MIN_WAVES 1
+#endif
+
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((plane_block<T, N>())) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
+__global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
     constexpr int L = plane_lanes<T, N>();
     constexpr int P = N / L;
     constexpr int LD = N + 1;
@@ -376,12 +302,14 @@ __global__ void __launch_bounds__((plane_block<T, N>())) kp_fast(const KPArgs<T>
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
-            cpx<T> xa[P], xb[P];
+            cpx<T> xa[P], xb[P], fa[P], fb[P];
             if (act) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    xa[q] = a.in[offa + row * N + s + L * q];
-                    xb[q] = a.in[offb + row * N + s + L * q];
+                    fa[q] = a.in[offa + row * N + s + L * q];
+                    fb[q] = a.in[offb + row * N + s + L * q];
+                    xa[q] = fa[q];
+                    xb[q] = fb[q];
                 }
                 lane_fwd<T, P, L>(xa, tab, s);
                 lane_fwd<T, P, L>(xb, tab, s);
@@ -439,7 +367,7 @@ __global__ void __launch_bounds__((plane_block<T, N>())) kp_fast(const KPArgs<T>
                         Tb = Tb + a.G[lofb + pt];
                     }
                     const long long ea = offa + pt, eb = offb + pt;
-                    point_epilogue<T, MODE>(a, pr, Ta, Tb, a.in[ea], a.in[eb], ea, eb, (long long)z * nxy + pt,
+                    point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
                                             coef, cdt, dn[q], dkr[q], dki[q], ekin);
                 }
             }
