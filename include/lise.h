@@ -118,12 +118,17 @@ typedef struct {
  *                -1 = never (always the z-axis kernel plus plane kernel)
  *   generic    : 1 = use the runtime-sized LDS FFT kernels even where a
  *                size-specialised register-FFT kernel exists (sides 8, 16,
- *                20, 24, 32, 48, 64; square xy-planes for the plane kernel) */
+ *                20, 24, 32, 48, 64; square xy-planes for the plane kernel)
+ *   no_overlap : 1 = run the z-axis kernel on the context stream; 0 = run it
+ *                one chunk ahead on an internal stream of default priority
+ *                (two z-scratch buffers, ordered by events) */
 typedef struct {
     int32_t chunk_qpwf;
     int32_t jgroup;
     int32_t fused;
     int32_t generic;
+    int32_t no_overlap;
+    int32_t reserved;
 } lise_tuning;
 
 /* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the

@@ -97,8 +97,12 @@ struct lise_ctx {
     size_t lds_limit = 65536;
 
     void* buf[7] = {nullptr};  // 0,1: y ring; 2..5: derivative ring; 6: p - c
-    void* G = nullptr;         // z-axis scratch, chunk qpwfs
-    long long g_cap = 0;       // qpwfs G holds
+    void* G = nullptr;         // z-axis scratch, chunk qpwfs (current buffer)
+    void* Gbuf[2] = {nullptr, nullptr};   // double buffer when the z kernel runs ahead
+    long long g_cap = 0;       // qpwfs each G buffer holds
+    hipStream_t s2 = nullptr;  // internal stream of the z-axis kernel (default priority)
+    hipEvent_t ev_start = nullptr, ev_kz[2] = {nullptr, nullptr}, ev_kp[2] = {nullptr, nullptr};
+    int overlap = 1;
     double* dpart = nullptr;   // density partial slots
     int slot_cap = 0;
     double* dens_cur = nullptr;
@@ -166,7 +170,7 @@ template <typename T>
 cpx<T>* S(lise_ctx* c, int i) { return reinterpret_cast<cpx<T>*>(c->buf[i]); }
 
 // ---- profiling -------------------------------------------------------------
-void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev) {
+void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev, hipStream_t st) {
     *ev = nullptr;
     if (!c->prof.on) return;
     if (c->prof.used + 2 > c->prof.pool.size()) {
@@ -174,16 +178,18 @@ void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev) {
         return;
     }
     *ev = c->prof.pool[c->prof.used];
-    (void)hipEventRecord(*ev, c->stream);
+    (void)hipEventRecord(*ev, st);
     (void)cls;
 }
-void prof_end(lise_ctx* c, int cls, hipEvent_t a) {
+void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev) { prof_begin(c, cls, ev, c->stream); }
+void prof_end(lise_ctx* c, int cls, hipEvent_t a, hipStream_t st) {
     if (!a) return;
     hipEvent_t b = c->prof.pool[c->prof.used + 1];
     c->prof.used += 2;
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, st);
     c->prof.recs.push_back({cls, a, b});
 }
+void prof_end(lise_ctx* c, int cls, hipEvent_t a) { prof_end(c, cls, a, c->stream); }
 
 int check_launch(lise_ctx* c, const char* what) {
     hipError_t e = hipGetLastError();
@@ -267,10 +273,16 @@ int configure(lise_ctx* c) {
     const int slots = (int)((chunk + c->jg - 1) / c->jg);
     const long long dens_slots = std::max<long long>(slots, (c->M + c->jg - 1) / c->jg);
     if (!c->fused && c->g_cap < chunk) {
-        dfree(&c->G);
-        CHK(dalloc(c, &c->G, (size_t)chunk * c->per * c->esz));
+        dfree(&c->Gbuf[0]);
+        dfree(&c->Gbuf[1]);
+        c->G = nullptr;
+        c->g_cap = 0;
+        CHK(dalloc(c, &c->Gbuf[0], (size_t)chunk * c->per * c->esz));
+        if (c->overlap) CHK(dalloc(c, &c->Gbuf[1], (size_t)chunk * c->per * c->esz));
         c->g_cap = chunk;
     }
+    if (!c->fused && c->overlap && !c->Gbuf[1]) CHK(dalloc(c, &c->Gbuf[1], (size_t)c->g_cap * c->per * c->esz));
+    c->G = c->Gbuf[0];
     if (c->slot_cap < dens_slots) {
         dfree(reinterpret_cast<void**>(&c->dpart));
         CHK(dalloc(c, reinterpret_cast<void**>(&c->dpart), (size_t)dens_slots * 3 * c->N * sizeof(double)));
@@ -384,7 +396,7 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
 }
 
 template <typename T>
-int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k) {
+int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, hipStream_t st) {
     if (c->fast_z) {
         KZFastArgs<T> f;
         f.nxy = (long long)c->lat.nx * c->lat.ny;
@@ -396,20 +408,20 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k) {
         f.cz = T(2.0 * pi * pi / (lz * lz) / c->lat.nz);
         f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
         f.in = in;
-        f.G = reinterpret_cast<cpx<T>*>(c->G);
+        f.G = reinterpret_cast<cpx<T>*>(Gdst);
         dim3 grid((unsigned)((f.ncols + kThreads - 1) / kThreads));
         hipEvent_t ev;
-        prof_begin(c, 1, &ev);
+        prof_begin(c, 1, &ev, st);
         switch (c->lat.nz) {
-            case 8: hipLaunchKernelGGL((kz_fast<T, 8>), grid, dim3(kThreads), 0, c->stream, f); break;
-            case 16: hipLaunchKernelGGL((kz_fast<T, 16>), grid, dim3(kThreads), 0, c->stream, f); break;
-            case 20: hipLaunchKernelGGL((kz_fast<T, 20>), grid, dim3(kThreads), 0, c->stream, f); break;
-            case 24: hipLaunchKernelGGL((kz_fast<T, 24>), grid, dim3(kThreads), 0, c->stream, f); break;
-            case 32: hipLaunchKernelGGL((kz_fast<T, 32>), grid, dim3(kThreads), 0, c->stream, f); break;
-            case 48: hipLaunchKernelGGL((kz_fast<T, 48>), grid, dim3(kThreads), 0, c->stream, f); break;
-            default: hipLaunchKernelGGL((kz_fast<T, 64>), grid, dim3(kThreads), 0, c->stream, f); break;
+            case 8: hipLaunchKernelGGL((kz_fast<T, 8>), grid, dim3(kThreads), 0, st, f); break;
+            case 16: hipLaunchKernelGGL((kz_fast<T, 16>), grid, dim3(kThreads), 0, st, f); break;
+            case 20: hipLaunchKernelGGL((kz_fast<T, 20>), grid, dim3(kThreads), 0, st, f); break;
+            case 24: hipLaunchKernelGGL((kz_fast<T, 24>), grid, dim3(kThreads), 0, st, f); break;
+            case 32: hipLaunchKernelGGL((kz_fast<T, 32>), grid, dim3(kThreads), 0, st, f); break;
+            case 48: hipLaunchKernelGGL((kz_fast<T, 48>), grid, dim3(kThreads), 0, st, f); break;
+            default: hipLaunchKernelGGL((kz_fast<T, 64>), grid, dim3(kThreads), 0, st, f); break;
         }
-        prof_end(c, 1, ev);
+        prof_end(c, 1, ev, st);
         return check_launch(c, "kz_fast");
     }
     KZArgs<T> a;
@@ -426,27 +438,48 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k) {
     const double lz = c->lat.nz * c->lat.a;
     a.cz = T(2.0 * pi * pi / (lz * lz) / c->lat.nz);
     a.in = in;
-    a.G = reinterpret_cast<cpx<T>*>(c->G);
+    a.G = reinterpret_cast<cpx<T>*>(Gdst);
     dim3 grid(c->lat.ny / c->yb, (unsigned)(k * c->C));
     const size_t lds = kz_lds_bytes(c, c->yb);
     hipEvent_t ev;
-    prof_begin(c, 1, &ev);
+    prof_begin(c, 1, &ev, st);
     if (lds > 65536) (void)hipFuncSetAttribute((const void*)kz_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((kz_kernel<T>), grid, dim3(kThreads), lds, c->stream, a);
-    prof_end(c, 1, ev);
+    hipLaunchKernelGGL((kz_kernel<T>), grid, dim3(kThreads), lds, st, a);
+    prof_end(c, 1, ev, st);
     return check_launch(c, "kz_kernel");
 }
 
 // One Hamiltonian application over all qpwfs [first, first+count) in chunks:
-// z-axis kernel (unless fused) then the plane kernel of the given mode.
+// z-axis kernel (unless fused) then the plane kernel of the given mode.  With
+// overlap on, the z-axis kernel of chunk c+1 runs on the internal stream
+// while the plane kernel of chunk c runs on the context stream; the two
+// z-scratch buffers alternate and events order every reuse.
 template <typename T, int MODE>
 int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int cls) {
     const int dens = a.dens_src;
+    const bool ov = c->overlap && !c->fused && c->s2;
+    if (ov) {
+        HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->s2, c->ev_start, 0));
+    }
     for (long long j0 = first, ci = 0; j0 < first + count; j0 += c->chunk, ++ci) {
         const int k = (int)std::min<long long>(c->chunk, first + count - j0);
-        if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k));
+        const int b = ov ? (int)(ci & 1) : 0;
+        void* Gb = c->Gbuf[b];
+        if (!c->fused) {
+            if (ov) {
+                if (ci >= 2) HIPCHK(c, hipStreamWaitEvent(c->s2, c->ev_kp[b], 0));
+                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->s2));
+                HIPCHK(c, hipEventRecord(c->ev_kz[b], c->s2));
+                HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_kz[b], 0));
+            } else {
+                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->stream));
+            }
+        }
+        a.G = reinterpret_cast<const cpx<T>*>(Gb);
         a.accumulate = (dens && ci > 0) ? 1 : 0;
         CHK((launch_kp_t<T, MODE>(c, a, j0, k, cls)));
+        if (ov) HIPCHK(c, hipEventRecord(c->ev_kp[b], c->stream));
     }
     return LISE_OK;
 }
@@ -679,7 +712,8 @@ int kinetic_energy_t(lise_ctx* c, double* ekin) {
     double sum = 0.0;
     for (long long j0 = 0; j0 < c->M; j0 += c->chunk) {
         const int k = (int)std::min<long long>(c->chunk, c->M - j0);
-        if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k));
+        if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k, c->Gbuf[0], c->stream));
+        a.G = reinterpret_cast<const cpx<T>*>(c->Gbuf[0]);
         CHK((launch_kp_t<T, KP_KINETIC>(c, a, j0, k, 3)));
         const long long nwg = (long long)(c->lat.nz / c->zb) * ((k + c->jg - 1) / c->jg);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->red, nwg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -846,6 +880,13 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     if (rc) return bail(rc);
     e = hipMemset(c->bad, 0, sizeof(int));
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipMemset: %s", hipGetErrorString(e)));
+    e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&c->ev_kz[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_kp[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "stream/event creation: %s", hipGetErrorString(e)));
     rc = configure(c);
     if (rc) return bail(rc);
     *out = c;
@@ -1004,10 +1045,12 @@ int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     if (!c || !t) return LISE_E_ARG;
     if (t->chunk_qpwf < 0 || t->jgroup < 0) return fail(c, LISE_E_ARG, "negative tuning value");
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->s2) HIPCHK(c, hipStreamSynchronize(c->s2));
     c->chunk = t->chunk_qpwf;
     if (t->jgroup > 0) c->jg = t->jgroup;
     c->fused_pref = (t->fused < 0) ? 0 : 1;
     c->generic = t->generic ? 1 : 0;
+    c->overlap = t->no_overlap ? 0 : 1;
     return configure(c);
 }
 
@@ -1046,7 +1089,7 @@ int lise_profile_read(lise_ctx* c, int32_t which, int64_t* launches, double* tot
 int lise_memory(const lise_ctx* c, int64_t* bytes) {
     if (!c || !bytes) return LISE_E_ARG;
     long long b = 7LL * c->M * c->per * (long long)c->esz;
-    b += c->g_cap * c->per * (long long)c->esz;
+    b += (c->Gbuf[1] ? 2 : 1) * c->g_cap * c->per * (long long)c->esz;
     b += (long long)c->slot_cap * 3 * c->N * 8;
     b += 10LL * c->N * 8;
     *bytes = b;
@@ -1061,8 +1104,17 @@ void lise_free(lise_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->s2) (void)hipStreamSynchronize(c->s2);
     for (auto& p : c->buf) dfree(&p);
-    dfree(&c->G);
+    dfree(&c->Gbuf[0]);
+    dfree(&c->Gbuf[1]);
+    c->G = nullptr;
+    if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+    for (int i = 0; i < 2; ++i) {
+        if (c->ev_kz[i]) (void)hipEventDestroy(c->ev_kz[i]);
+        if (c->ev_kp[i]) (void)hipEventDestroy(c->ev_kp[i]);
+    }
     dfree(reinterpret_cast<void**>(&c->dpart));
     dfree(reinterpret_cast<void**>(&c->dens_cur));
     dfree(reinterpret_cast<void**>(&c->dens_tmp));

@@ -54,7 +54,8 @@ class Obs(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("chunk_qpwf", ct.c_int32), ("jgroup", ct.c_int32),
-                ("fused", ct.c_int32), ("generic", ct.c_int32)]
+                ("fused", ct.c_int32), ("generic", ct.c_int32),
+                ("no_overlap", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 _lib = None
@@ -200,8 +201,8 @@ class Context:
     def set_stream(self, stream):
         self._check(self.lib.lise_set_stream(self._h, ct.c_void_p(stream or 0)), "lise_set_stream")
 
-    def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0, generic=0):
-        t = Tuning(chunk_qpwf, jgroup, fused, generic)
+    def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0, generic=0, no_overlap=0):
+        t = Tuning(chunk_qpwf, jgroup, fused, generic, no_overlap, 0)
         self._check(self.lib.lise_set_tuning(self._h, ct.byref(t)), "lise_set_tuning")
 
     def profile(self, enable):

@@ -65,6 +65,8 @@ APPLY_CASES = [
     (48, 48, 48, 1.0, 2, 2, 1, {"generic": 1}),
     (64, 64, 64, 1.0, 4, 1, 1, {}),
     (8, 8, 8, 1.0, 2, 4, 0, {"fused": -1, "generic": 0}),
+    (32, 32, 32, 1.0, 2, 5, 0, {"chunk_qpwf": 2, "jgroup": 1}),
+    (32, 32, 32, 1.0, 2, 5, 0, {"chunk_qpwf": 2, "jgroup": 1, "no_overlap": 1}),
 ]
 
 
@@ -259,6 +261,22 @@ def test_single_qpwf_and_odd_lattice(lise):
     ev = oracle.Evolver(lat, fn, psi)
     ev.step(0.01, 10)
     assert rel_l2(got, ev.y) < 1e-12
+
+
+def test_overlap_matches_serial_bitwise(lise):
+    """The z kernel running one chunk ahead on the internal stream gives bit-identical results."""
+    w = wl.config2(M=40, n=16, steps=10)
+    psi = w.qpwfs()
+    outs = []
+    for no_ov in (0, 1):
+        say(f"overlap={1 - no_ov} 16^3 M=40 chunk 7, 6 steps")
+        ctx = lise.Context(w.lattice, w.M, w.functional)
+        ctx.set_tuning(chunk_qpwf=7, jgroup=3, no_overlap=no_ov)
+        ctx.set_qpwf(0, psi)
+        ctx.step(w.dt, 6)
+        outs.append(ctx.get_qpwf(0, w.M))
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_deterministic_repeats(lise):
