@@ -121,14 +121,17 @@ typedef struct {
  *                20, 24, 32, 48, 64; square xy-planes for the plane kernel)
  *   no_overlap : 1 = run the z-axis kernel on the context stream; 0 = run it
  *                one chunk ahead on an internal stream of default priority
- *                (two z-scratch buffers, ordered by events) */
+ *                (two z-scratch buffers, ordered by events)
+ *   graph      : 1 = lise_step captures four ABM steps (one period of the
+ *                buffer ring) in a HIP graph and replays it; results are
+ *                bit-identical to eager stepping */
 typedef struct {
     int32_t chunk_qpwf;
     int32_t jgroup;
     int32_t fused;
     int32_t generic;
     int32_t no_overlap;
-    int32_t reserved;
+    int32_t graph;
 } lise_tuning;
 
 /* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the
@@ -201,6 +204,30 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
  * were recorded since the previous read (the event pool is fixed). */
 int lise_profile(lise_ctx *c, int32_t enable);
 int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
+
+/* Timed search over launch tuning (chunk size, qpwfs per plane workgroup,
+ * z-kernel overlap) for this system: each candidate runs one untimed and
+ * `trial_steps` timed ABM steps with step size dt on the live state (the
+ * state advances; results change only in rounding), the fastest is kept and
+ * written to *chosen (may be NULL).  Runs the start-up first if needed.
+ * Errors: ARG, STATE, HIP, NAN. */
+int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);
+
+/* Batch of independent systems (for example different lattices and qpwf
+ * counts) advanced together.  lise_batch_create takes nsys distinct contexts
+ * on the current device and moves all of them onto `hip_stream`; the
+ * contexts stay owned by the caller and usable (densities, observables) but
+ * must not be freed before the batch.  lise_batch_step runs each system's
+ * start-up if needed, then captures kPeriod = 4 ABM steps of every system
+ * into one HIP graph with one branch per system (branches run concurrently)
+ * and replays it; leftover steps run eagerly.  The graph is re-captured when
+ * dt, the tuning, or a system's ring of buffers changed since the capture.
+ * Errors: ARG, STATE, HIP, NAN (text from lise_batch_last_error). */
+typedef struct lise_batch lise_batch;
+int lise_batch_create(lise_batch **out, int32_t nsys, lise_ctx *const *ctxs, void *hip_stream);
+int lise_batch_step(lise_batch *b, double dt, int64_t nsteps);
+const char *lise_batch_last_error(const lise_batch *b);
+void lise_batch_free(lise_batch *b);
 
 /* Bytes of device memory the context holds. */
 int lise_memory(const lise_ctx *c, int64_t *bytes);

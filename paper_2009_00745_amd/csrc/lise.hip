@@ -117,6 +117,7 @@ struct lise_ctx {
     double* norms = nullptr;
     double* norms0 = nullptr;
     int* bad = nullptr;
+    double* dtime = nullptr;   // device copy of t (advanced by tick_kernel)
     AxisPlan px, py, pz;
 
     // tuning
@@ -139,6 +140,11 @@ struct lise_ctx {
     int dn = 0;   // derivative slot receiving y'_n (0..3)
 
     Prof prof;
+    bool capturing = false;
+    int use_graph = 0;            // lise_step replays a captured 4-step graph
+    hipGraphExec_t gexec = nullptr;
+    long long gsig = -1;          // ring state the graph was captured in
+    long long config_version = 0;
     char err[512] = {0};
 };
 
@@ -172,7 +178,7 @@ cpx<T>* S(lise_ctx* c, int i) { return reinterpret_cast<cpx<T>*>(c->buf[i]); }
 // ---- profiling -------------------------------------------------------------
 void prof_begin(lise_ctx* c, int cls, hipEvent_t* ev, hipStream_t st) {
     *ev = nullptr;
-    if (!c->prof.on) return;
+    if (!c->prof.on || c->capturing) return;
     if (c->prof.used + 2 > c->prof.pool.size()) {
         c->prof.overflow = true;
         return;
@@ -226,8 +232,42 @@ size_t fast_kp_lds(const lise_ctx* c) {
     return (n + 2 * n * (n + 1)) * c->esz;
 }
 
+// Allow every kernel that takes dynamic LDS to use the device's whole LDS,
+// once per process (outside any stream capture).
+template <typename T, int NS>
+void set_fast_attrs(int lim) {
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+template <typename T>
+void set_type_attrs(int lim) {
+    set_fast_attrs<T, 8>(lim);
+    set_fast_attrs<T, 16>(lim);
+    set_fast_attrs<T, 20>(lim);
+    set_fast_attrs<T, 24>(lim);
+    set_fast_attrs<T, 32>(lim);
+    set_fast_attrs<T, 48>(lim);
+    set_fast_attrs<T, 64>(lim);
+    const void* g[] = {(const void*)kp_kernel<T, 0, 4>, (const void*)kp_kernel<T, 1, 4>, (const void*)kp_kernel<T, 2, 4>,
+                       (const void*)kp_kernel<T, 3, 4>, (const void*)kp_kernel<T, 0, 16>, (const void*)kp_kernel<T, 1, 16>,
+                       (const void*)kp_kernel<T, 2, 16>, (const void*)kp_kernel<T, 3, 16>, (const void*)kz_kernel<T>};
+    for (const void* f : g) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+void set_all_attrs(int lim) {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    set_type_attrs<double>(lim);
+    set_type_attrs<float>(lim);
+}
+
 // Choose launch geometry and (re)allocate scratch for the current tuning.
 int configure(lise_ctx* c) {
+    c->config_version += 1;
     const int nx = c->lat.nx, ny = c->lat.ny, nz = c->lat.nz;
     const long long nxy = (long long)nx * ny;
     // fused: the whole cube of one component pair in LDS (two buffers)
@@ -353,8 +393,6 @@ template <typename T, int MODE, int NS>
 void launch_kp_fast_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
     constexpr int block = plane_block<T, NS>();
     const size_t lds = std::max(kp_fast_lds<T, NS>(), (size_t)block * sizeof(double));
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((kp_fast<T, NS, MODE>), grid, dim3(block), lds, c->stream, a,
                        reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
 }
@@ -385,10 +423,8 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     hipEvent_t ev;
     prof_begin(c, cls, &ev);
     if (c->ppt == 4) {
-        if (lds > 65536) (void)hipFuncSetAttribute((const void*)kp_kernel<T, MODE, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((kp_kernel<T, MODE, 4>), grid, dim3(kThreads), lds, c->stream, a);
     } else {
-        if (lds > 65536) (void)hipFuncSetAttribute((const void*)kp_kernel<T, MODE, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL((kp_kernel<T, MODE, 16>), grid, dim3(kThreads), lds, c->stream, a);
     }
     prof_end(c, cls, ev);
@@ -443,7 +479,6 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
     const size_t lds = kz_lds_bytes(c, c->yb);
     hipEvent_t ev;
     prof_begin(c, 1, &ev, st);
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kz_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((kz_kernel<T>), grid, dim3(kThreads), lds, st, a);
     prof_end(c, 1, ev, st);
     return check_launch(c, "kz_kernel");
@@ -491,12 +526,13 @@ int slots_used(const lise_ctx* c, long long count) {
 
 // Reduce density partials (nslots > 0) or reuse dens (nslots = 0), optional
 // average, then fields at time t.
-int launch_fields(lise_ctx* c, int nslots, const double* avg_with, double* dens, double* V, double* D, double t) {
+// toff: time offset from the system's device-side time t_n
+int launch_fields(lise_ctx* c, int nslots, const double* avg_with, double* dens, double* V, double* D, double toff) {
     dim3 grid((unsigned)((c->N + kThreads - 1) / kThreads));
     hipEvent_t ev;
     prof_begin(c, 2, &ev);
     hipLaunchKernelGGL(fields_kernel, grid, dim3(kThreads), 0, c->stream, c->dpart, nslots, c->N, avg_with, dens, V,
-                       D, field_params(c), t, c->bad);
+                       D, field_params(c), c->dtime, toff, c->bad);
     prof_end(c, 2, ev);
     return check_launch(c, "fields_kernel");
 }
@@ -508,7 +544,14 @@ int dens_direct_t(lise_ctx* c, const cpx<T>* state) {
     hipLaunchKernelGGL((dens_partial_kernel<T>), grid, dim3(kThreads), 0, c->stream, state, c->C, c->N, c->M, c->jg,
                        c->C == 2 ? c->fn.w : 1.0, c->dpart);
     CHK(check_launch(c, "dens_partial_kernel"));
-    return launch_fields(c, (int)slots, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t);
+    return launch_fields(c, (int)slots, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0);
+}
+
+// t_n -> t_n + dt on the device and on the host (the same float64 addition).
+int tick(lise_ctx* c, double dt) {
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, c->stream, c->dtime, dt);
+    c->t += dt;
+    return check_launch(c, "tick_kernel");
 }
 
 int check_bad(lise_ctx* c) {
@@ -564,7 +607,7 @@ template <typename T>
 int startup_t(lise_ctx* c, double dt) {
     CHK(ensure_fields_t<T>(c));
     // fields of y_0 at t_0
-    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
     int ys = c->iy;             // buffer of Y_s
     const int term = 6;         // p - c slot used as term buffer during start-up
     for (int s = 0; s < 3; ++s) {
@@ -572,12 +615,12 @@ int startup_t(lise_ctx* c, double dt) {
         // predictor with H(t_s); stores y'_s in derivative slot s
         CHK(taylor_t<T>(c, S<T>(c, ys), S<T>(c, term), S<T>(c, acc), S<T>(c, 2 + s), c->V_cur, c->D_cur, dt));
         // corrector fields from (n_pre + n_s)/2 at t_s + dt/2
-        CHK(launch_fields(c, slots_used(c, c->M), c->dens_cur, c->dens_tmp, c->V_tmp, c->D_tmp, c->t + 0.5 * dt));
+        CHK(launch_fields(c, slots_used(c, c->M), c->dens_cur, c->dens_tmp, c->V_tmp, c->D_tmp, 0.5 * dt));
         CHK(taylor_t<T>(c, S<T>(c, ys), S<T>(c, term), S<T>(c, acc), nullptr, c->V_tmp, c->D_tmp, dt));
-        c->t += dt;
+        CHK(tick(c, dt));
         c->step += 1;
         // densities of Y_{s+1} -> fields at t_{s+1}
-        CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+        CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
         ys = acc;
     }
     // y_n = Y_3 (buffer ys), y_{n-1} = Y_2; derivatives y'_0..y'_2 in slots 0..2
@@ -616,7 +659,7 @@ int abm_step_t(lise_ctx* c) {
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0)));
     }
-    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, c->t + dt));
+    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, dt));
     // phase 2: H m -> m', y_{n+1}, p_{n+1} - c_{n+1}; densities of y_{n+1}
     {
         KPArgs<T> a = kp_base<T>(c);
@@ -630,17 +673,92 @@ int abm_step_t(lise_ctx* c) {
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0)));
     }
-    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t + dt));
+    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, dt));
+    CHK(tick(c, dt));
     c->iy = ym1;
     c->dn = (c->dn + 1) % 4;
-    c->t += dt;
     c->step += 1;
+    return LISE_OK;
+}
+
+// Host bookkeeping of one ABM step whose device work ran inside a graph.
+void advance_host(lise_ctx* c, double dt) {
+    c->t += dt;
+    c->iy = 1 - c->iy;
+    c->dn = (c->dn + 1) % 4;
+    c->step += 1;
+}
+
+struct HostState {
+    double t;
+    long long step;
+    int iy, dn;
+};
+HostState save_host(const lise_ctx* c) { return {c->t, c->step, c->iy, c->dn}; }
+void restore_host(lise_ctx* c, const HostState& h) {
+    c->t = h.t;
+    c->step = h.step;
+    c->iy = h.iy;
+    c->dn = h.dn;
+}
+
+long long ring_sig(const lise_ctx* c) { return (c->config_version * 4 + c->dn) * 2 + c->iy; }
+
+int abm_step_any(lise_ctx* c) { return c->prec == LISE_FP64 ? abm_step_t<double>(c) : abm_step_t<float>(c); }
+
+// Capture kPeriod ABM steps of one system on its current stream (which must
+// be capturing).  The ring of buffers returns to its state after kPeriod
+// steps, so the captured work can be replayed.  Host bookkeeping is restored.
+constexpr int kPeriod = 4;
+int capture_period(lise_ctx* c) {
+    const HostState h = save_host(c);
+    c->capturing = true;
+    int rc = LISE_OK;
+    for (int i = 0; i < kPeriod && rc == LISE_OK; ++i) rc = abm_step_any(c);
+    c->capturing = false;
+    restore_host(c, h);
+    return rc;
+}
+
+int ensure_graph(lise_ctx* c) {
+    const long long sig = ring_sig(c);
+    if (c->gexec && c->gsig == sig) return LISE_OK;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = capture_period(c);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc != LISE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, LISE_E_HIP, "stream capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, LISE_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    c->gsig = sig;
     return LISE_OK;
 }
 
 template <typename T>
 int step_t(lise_ctx* c, double dt, long long nsteps) {
-    if (!c->hist || c->dt_hist != dt) CHK(startup_t<T>(c, dt));
+    if (!c->hist || c->dt_hist != dt) {
+        CHK(startup_t<T>(c, dt));
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+    }
+    if (c->use_graph && nsteps >= 2 * kPeriod) {
+        CHK(ensure_graph(c));
+        for (; nsteps >= kPeriod; nsteps -= kPeriod) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            for (int i = 0; i < kPeriod; ++i) advance_host(c, dt);
+        }
+    }
     for (long long s = 0; s < nsteps; ++s) CHK(abm_step_t<T>(c));
     return check_bad(c);
 }
@@ -648,7 +766,7 @@ int step_t(lise_ctx* c, double dt, long long nsteps) {
 template <typename T>
 int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_is_device) {
     CHK(ensure_fields_t<T>(c));
-    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
     // H psi into the p - c slot when there is no history, else a temporary
     void* tmp = nullptr;
     cpx<T>* dst;
@@ -733,7 +851,7 @@ int norms_t(lise_ctx* c, double* dst) {
 template <typename T>
 int observables_t(lise_ctx* c, lise_obs* o) {
     CHK(ensure_fields_t<T>(c));
-    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, c->t));
+    CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
     const int nblk = 256;
     if (c->red_cap < nblk * kNObs) {
         dfree(reinterpret_cast<void**>(&c->red));
@@ -790,6 +908,69 @@ int valid_dim(int n) {
 
 }  // namespace
 
+// A batch of independent systems advanced together: one graph launch runs
+// kPeriod ABM steps of every system, each system on its own branch.
+struct lise_batch {
+    std::vector<lise_ctx*> sys;
+    hipStream_t stream = nullptr;
+    std::vector<hipStream_t> fork;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<long long> gsig;
+    double gdt = 0.0;
+    char err[512] = {0};
+};
+
+namespace {
+
+int bfail(lise_batch* b, int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(b->err, sizeof(b->err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int batch_capture(lise_batch* b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "begin capture: %s", hipGetErrorString(e));
+    int rc = LISE_OK;
+    e = hipEventRecord(b->ev_fork, b->stream);
+    for (size_t i = 0; i < b->sys.size() && rc == LISE_OK && e == hipSuccess; ++i) {
+        lise_ctx* c = b->sys[i];
+        e = hipStreamWaitEvent(b->fork[i], b->ev_fork, 0);
+        if (e != hipSuccess) break;
+        c->stream = b->fork[i];
+        rc = capture_period(c);
+        c->stream = b->stream;
+        if (rc != LISE_OK) {
+            bfail(b, rc, "system %zu: %s", i, c->err);
+            break;
+        }
+        e = hipEventRecord(b->ev_join[i], b->fork[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (rc != LISE_OK || e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != LISE_OK) return rc;
+        return bfail(b, LISE_E_HIP, "batch capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "batch graph instantiation: %s", hipGetErrorString(e));
+    for (size_t i = 0; i < b->sys.size(); ++i) b->gsig[i] = ring_sig(b->sys[i]);
+    return LISE_OK;
+}
+
+}  // namespace
+
 // =============================================================================
 // C-ABI
 
@@ -828,6 +1009,7 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     e = hipGetDeviceProperties(&prop, c->device);
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e)));
     c->lds_limit = prop.sharedMemPerBlock;
+    set_all_attrs((int)c->lds_limit);
     // plans and twiddles
     std::vector<cpx<double>> tw;
     if (!make_plan(lat->nx, &c->px, &tw) || !make_plan(lat->ny, &c->py, &tw) || !make_plan(lat->nz, &c->pz, &tw))
@@ -877,8 +1059,10 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->norms), (size_t)c->M * sizeof(double));
     rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->norms0), (size_t)c->M * sizeof(double));
     rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->bad), sizeof(int));
+    rc = rc ? rc : dalloc(c, reinterpret_cast<void**>(&c->dtime), sizeof(double));
     if (rc) return bail(rc);
-    e = hipMemset(c->bad, 0, sizeof(int));
+    e = hipMemset(c->dtime, 0, sizeof(double));
+    if (e == hipSuccess) e = hipMemset(c->bad, 0, sizeof(int));
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipMemset: %s", hipGetErrorString(e)));
     e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming);
@@ -1030,6 +1214,8 @@ int lise_get_time(const lise_ctx* c, double* t, int64_t* step) {
 
 int lise_set_time(lise_ctx* c, double t) {
     if (!c || !std::isfinite(t)) return LISE_E_ARG;
+    HIPCHK(c, hipMemcpyAsync(c->dtime, &t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->t = t;
     c->hist = false;
     return LISE_OK;
@@ -1051,6 +1237,7 @@ int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     c->fused_pref = (t->fused < 0) ? 0 : 1;
     c->generic = t->generic ? 1 : 0;
     c->overlap = t->no_overlap ? 0 : 1;
+    c->use_graph = t->graph ? 1 : 0;
     return configure(c);
 }
 
@@ -1096,6 +1283,152 @@ int lise_memory(const lise_ctx* c, int64_t* bytes) {
     return LISE_OK;
 }
 
+int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, void* hip_stream) {
+    if (!out || nsys < 1 || !ctxs) return LISE_E_ARG;
+    *out = nullptr;
+    lise_batch* b = new (std::nothrow) lise_batch();
+    if (!b) return LISE_E_NOMEM;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < nsys; ++i) {
+        if (!ctxs[i]) {
+            delete b;
+            return LISE_E_ARG;
+        }
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) {
+                delete b;
+                return LISE_E_ARG;
+            }
+        b->sys.push_back(ctxs[i]);
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    b->fork.assign(nsys, nullptr);
+    b->ev_join.assign(nsys, nullptr);
+    b->gsig.assign(nsys, -1);
+    for (int i = 0; i < nsys && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&b->fork[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        lise_batch_free(b);
+        return LISE_E_HIP;
+    }
+    // every system now enqueues on the batch stream
+    for (lise_ctx* c : b->sys) {
+        (void)hipStreamSynchronize(c->stream);
+        c->stream = b->stream;
+    }
+    *out = b;
+    return LISE_OK;
+}
+
+int lise_batch_step(lise_batch* b, double dt, int64_t nsteps) {
+    if (!b) return LISE_E_ARG;
+    if (!std::isfinite(dt) || dt == 0.0 || nsteps < 0) return bfail(b, LISE_E_ARG, "bad dt or nsteps");
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        lise_ctx* c = b->sys[i];
+        c->stream = b->stream;
+        if (c->n_set < c->M) return bfail(b, LISE_E_STATE, "system %zu: qpwfs not fully set", i);
+        if (!c->hist || c->dt_hist != dt) {
+            int rc = c->prec == LISE_FP64 ? startup_t<double>(c, dt) : startup_t<float>(c, dt);
+            if (rc != LISE_OK) return bfail(b, rc, "system %zu start-up: %s", i, c->err);
+        }
+    }
+    if (nsteps >= kPeriod) {
+        bool stale = !b->gexec || b->gdt != dt;
+        for (size_t i = 0; i < b->sys.size() && !stale; ++i) stale = b->gsig[i] != ring_sig(b->sys[i]);
+        if (stale) {
+            int rc = batch_capture(b);
+            if (rc != LISE_OK) return rc;
+            b->gdt = dt;
+        }
+        for (; nsteps >= kPeriod; nsteps -= kPeriod) {
+            hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+            if (e != hipSuccess) return bfail(b, LISE_E_HIP, "graph launch: %s", hipGetErrorString(e));
+            for (lise_ctx* c : b->sys)
+                for (int i = 0; i < kPeriod; ++i) advance_host(c, dt);
+        }
+    }
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        lise_ctx* c = b->sys[i];
+        for (long long s = 0; s < nsteps; ++s) {
+            int rc = abm_step_any(c);
+            if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", i, c->err);
+        }
+    }
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        int rc = check_bad(b->sys[i]);
+        if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", i, b->sys[i]->err);
+    }
+    return LISE_OK;
+}
+
+const char* lise_batch_last_error(const lise_batch* b) { return b ? b->err : "null batch"; }
+
+void lise_batch_free(lise_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (hipStream_t s : b->fork)
+        if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    delete b;
+}
+
+int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chosen) {
+    if (!c || trial_steps < 1) return LISE_E_ARG;
+    if (!std::isfinite(dt) || dt == 0.0) return fail(c, LISE_E_ARG, "dt must be finite and non-zero");
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set");
+    CHK(lise_step(c, dt, 0));   // start-up if needed
+    const long long per_bytes = c->per * (long long)c->esz;
+    const long long gib = std::max<long long>(1, (1LL << 30) / std::max<long long>(per_bytes, 1));
+    std::vector<long long> chunks = {std::min<long long>(c->M, gib), std::min<long long>(c->M, 2 * gib),
+                                     std::min<long long>(c->M, std::max<long long>(16, gib / 4))};
+    std::sort(chunks.begin(), chunks.end());
+    chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
+    const int jgs[] = {8, 16, 32};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    lise_tuning best{};
+    float best_ms = 1e30f;
+    int rc = LISE_OK;
+    for (long long ch : chunks)
+        for (int jg : jgs)
+            for (int nov = 0; nov < 2 && rc == LISE_OK; ++nov) {
+                if (c->fused && nov) continue;
+                lise_tuning t{};
+                t.chunk_qpwf = (int32_t)ch;
+                t.jgroup = jg;
+                t.fused = c->fused_pref ? 0 : -1;
+                t.generic = c->generic;
+                t.no_overlap = nov;
+                t.graph = c->use_graph;
+                rc = lise_set_tuning(c, &t);
+                if (rc == LISE_OK) rc = lise_step(c, dt, 1);
+                if (rc != LISE_OK) break;
+                (void)hipEventRecord(e0, c->stream);
+                rc = lise_step(c, dt, trial_steps);
+                (void)hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rc == LISE_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LISE_OK) return rc;
+    CHK(lise_set_tuning(c, &best));
+    if (chosen) *chosen = best;
+    return LISE_OK;
+}
+
 const char* lise_last_error(const lise_ctx* c) { return c ? c->err : "null context"; }
 
 const char* lise_version(void) { return kVersion; }
@@ -1127,6 +1460,8 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->norms));
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->bad));
+    dfree(reinterpret_cast<void**>(&c->dtime));
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& ev : c->prof.pool) (void)hipEventDestroy(ev);
     delete c;
 }

@@ -606,13 +606,17 @@ __device__ __forceinline__ double ext_potential(const FieldParams& f, long long 
     return f.extA * ramp * exp(-d2 / (2.0 * f.extw * f.extw));
 }
 
+// The time comes from device memory (tdev[0] + toff) so that a captured
+// graph of whole steps stays valid on every replay.
 __global__ void __launch_bounds__(256) fields_kernel(const double* __restrict__ dpart, int nslots, long long N,
                                                      const double* __restrict__ avg_with,
                                                      double* __restrict__ dens_out, double* __restrict__ V,
-                                                     double* __restrict__ D, FieldParams fp, double t,
+                                                     double* __restrict__ D, FieldParams fp,
+                                                     const double* __restrict__ tdev, double toff,
                                                      int* __restrict__ bad) {
     const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
+    const double t = tdev[0] + toff;
     double n, kr, ki;
     if (nslots > 0) {
         n = kr = ki = 0.0;
@@ -720,6 +724,11 @@ __global__ void __launch_bounds__(256) convert_kernel(const cpx<TI>* __restrict_
         const cpx<TI> v = in[e];
         out[e] = mk(TO(v.re), TO(v.im));
     }
+}
+
+// Advance the device-side time of a system by dt (one thread).
+__global__ void tick_kernel(double* __restrict__ t, double dt) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) t[0] = t[0] + dt;
 }
 
 __global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ p, long long n) {

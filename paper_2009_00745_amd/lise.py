@@ -21,7 +21,8 @@ ERRORS = {0: "OK", -1: "LISE_E_ARG", -2: "LISE_E_NOMEM", -3: "LISE_E_UNSUPPORTED
 SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_startup",
            "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
-           "lise_memory", "lise_last_error", "lise_version", "lise_free"]
+           "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune",
+           "lise_batch_create", "lise_batch_step", "lise_batch_last_error", "lise_batch_free"]
 
 
 class Lattice(ct.Structure):
@@ -55,7 +56,7 @@ class Obs(ct.Structure):
 class Tuning(ct.Structure):
     _fields_ = [("chunk_qpwf", ct.c_int32), ("jgroup", ct.c_int32),
                 ("fused", ct.c_int32), ("generic", ct.c_int32),
-                ("no_overlap", ct.c_int32), ("reserved", ct.c_int32)]
+                ("no_overlap", ct.c_int32), ("graph", ct.c_int32)]
 
 
 _lib = None
@@ -90,6 +91,11 @@ def load_library(path=LIB_PATH):
         "lise_last_error": ([P], ct.c_char_p),
         "lise_version": ([], ct.c_char_p),
         "lise_free": ([P], None),
+        "lise_autotune": ([P, ct.c_double, ct.c_int32, ct.POINTER(Tuning)], ct.c_int),
+        "lise_batch_create": ([ct.POINTER(P), ct.c_int32, ct.POINTER(P), P], ct.c_int),
+        "lise_batch_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
+        "lise_batch_last_error": ([P], ct.c_char_p),
+        "lise_batch_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -201,8 +207,8 @@ class Context:
     def set_stream(self, stream):
         self._check(self.lib.lise_set_stream(self._h, ct.c_void_p(stream or 0)), "lise_set_stream")
 
-    def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0, generic=0, no_overlap=0):
-        t = Tuning(chunk_qpwf, jgroup, fused, generic, no_overlap, 0)
+    def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0, generic=0, no_overlap=0, graph=0):
+        t = Tuning(chunk_qpwf, jgroup, fused, generic, no_overlap, graph)
         self._check(self.lib.lise_set_tuning(self._h, ct.byref(t)), "lise_set_tuning")
 
     def profile(self, enable):
@@ -215,10 +221,45 @@ class Context:
                     "lise_profile_read")
         return n.value, ms.value
 
+    def autotune(self, dt, trial_steps=2):
+        t = Tuning()
+        self._check(self.lib.lise_autotune(self._h, dt, trial_steps, ct.byref(t)), "lise_autotune")
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
     def memory(self):
         b = ct.c_int64()
         self._check(self.lib.lise_memory(self._h, ct.byref(b)), "lise_memory")
         return b.value
+
+
+class Batch:
+    """Independent systems advanced together by one graph per four ABM steps."""
+
+    def __init__(self, contexts, stream=None):
+        self.lib = load_library()
+        self.contexts = list(contexts)
+        arr = (ct.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        self._h = ct.c_void_p()
+        rc = self.lib.lise_batch_create(ct.byref(self._h), len(self.contexts), arr, ct.c_void_p(stream or 0))
+        if rc != 0:
+            raise LiseError(f"lise_batch_create failed: {ERRORS.get(rc, rc)}")
+
+    def step(self, dt, nsteps):
+        rc = self.lib.lise_batch_step(self._h, dt, nsteps)
+        if rc != 0:
+            msg = self.lib.lise_batch_last_error(self._h).decode()
+            raise LiseError(f"lise_batch_step: {ERRORS.get(rc, rc)}: {msg}")
+
+    def close(self):
+        if self._h:
+            self.lib.lise_batch_free(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version():

@@ -279,6 +279,80 @@ def test_overlap_matches_serial_bitwise(lise):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_graph_replay_matches_eager_bitwise(lise):
+    """Four-step graph replays (plus an eager remainder) equal eager stepping bit for bit,
+    including the time-dependent external well (time read from device memory)."""
+    w = wl.config2(M=20, n=16, steps=10)
+    psi = w.qpwfs()
+    outs = []
+    for graph in (0, 1):
+        say(f"graph={graph} 16^3 M=20, 11 steps")
+        ctx = lise.Context(w.lattice, w.M, w.functional)
+        ctx.set_tuning(chunk_qpwf=8, jgroup=3, graph=graph)
+        ctx.set_qpwf(0, psi)
+        ctx.step(w.dt, 11)
+        ctx.step(w.dt, 9)
+        outs.append((ctx.get_qpwf(0, w.M), ctx.densities()[0], ctx.time()))
+        ctx.close()
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def batch_systems():
+    specs = [(wl.config1(M=64), wl.FP64), (wl.config2(M=24, n=16), wl.FP64),
+             (wl.config3(M=16, n=20, precision=wl.FP32), wl.FP32), (wl.config4(M=12, n=8, precision=wl.FP64), wl.FP64)]
+    out = []
+    for w, prec in specs:
+        w.functional.precision = prec
+        out.append(w)
+    return out
+
+
+def test_batch_matches_individual_systems_bitwise(lise):
+    """A batch of uneven systems (lattices 8^3..20^3, C = 2 and 4, FP64 and FP32) stepped
+    through one graph equals each system stepped alone."""
+    systems = batch_systems()
+    dt = 0.002
+    say("batch of 4 systems, 10 steps")
+    ctxs = []
+    for w in systems:
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_qpwf(0, w.qpwfs())
+        ctxs.append(c)
+    b = lise.Batch(ctxs)
+    b.step(dt, 10)
+    got = [c.get_qpwf(0, w.M) for c, w in zip(ctxs, systems)]
+    b.close()
+    for c in ctxs:
+        c.close()
+    for w, g in zip(systems, got):
+        say(f"  alone: {w.name}")
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_qpwf(0, w.qpwfs())
+        c.step(dt, 10)
+        ref = c.get_qpwf(0, w.M)
+        c.close()
+        assert np.array_equal(g, ref), w.name
+    # and one of them against the oracle
+    w = systems[1]
+    ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
+    ev.step(dt, 10)
+    assert rel_l2(got[1], ev.y) < 1e-11
+
+
+def test_autotune_runs_and_keeps_invariants(lise):
+    w = wl.config2(M=64, n=16)
+    say("autotune 16^3 M=64")
+    ctx = lise.Context(w.lattice, w.M, w.functional)
+    ctx.set_qpwf(0, w.qpwfs())
+    t = ctx.autotune(w.dt, 1)
+    assert t["jgroup"] in (8, 16, 32) and t["chunk_qpwf"] >= 1
+    ctx.step(w.dt, 4)
+    o = ctx.observables()
+    assert o["norm_drift_max"] < 1e-10
+    ctx.close()
+
+
 def test_deterministic_repeats(lise):
     w = wl.config2(M=24, n=16, steps=10)
     psi = w.qpwfs()
