@@ -83,6 +83,46 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True):
     return ctx, t2 - t1, prof
 
 
+def run_batched(nsys, steps, warmup):
+    """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced by one
+    graph launch per four ABM steps, each system on its own graph branch."""
+    import torch
+    import workloads as wl
+    import paper_2009_00745_amd as lise
+    systems = wl.config5_systems(seed=0, nsys=nsys)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctxs = []
+    t0 = time.time()
+    for w in systems:
+        c = lise.Context(w.lattice, w.M, w.functional, stream=stream)
+        upload(c, w)
+        ctxs.append(c)
+    log(f"batched: {nsys} systems uploaded in {time.time() - t0:.1f}s")
+    b = lise.Batch(ctxs, stream=stream)
+    dt = systems[0].dt
+    b.step(dt, 4 * max(1, warmup))       # start-up, graph capture, warm-up replays
+    torch.cuda.synchronize()
+    nst = 4 * max(1, steps // 4)
+    t1 = time.perf_counter()
+    b.step(dt, nst)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    qsteps = sum(w.M for w in systems) * nst
+    sizes = {}
+    for w in systems:
+        sizes.setdefault(w.lattice.nx, [0, 0])
+        sizes[w.lattice.nx][0] += 1
+        sizes[w.lattice.nx][1] += w.M
+    b_alg = sum(w.M * 16 * 2 * w.lattice.n * 8 for w in systems) * nst / el
+    b.close()
+    for c in ctxs:
+        c.close()
+    return {"value": qsteps / el, "unit": "qpwf-steps/s", "systems": nsys, "steps": nst,
+            "ms_per_step": 1e3 * el / nst, "qpwf_total": sum(w.M for w in systems),
+            "lattices": {f"{k}^3": {"systems": v[0], "qpwfs": v[1]} for k, v in sorted(sizes.items())},
+            "step_hbm_frac": b_alg / HBM_PEAK}
+
+
 def cpu_baseline(w_name, M_sample, steps):
     """The oracle, unchanged, on M_sample qpwfs of the same workload."""
     import oracle
@@ -127,6 +167,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--batched", type=int, default=16,
+                    help="number of independent systems in the batched variant (0 = skip; 64 = full workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -201,6 +243,9 @@ def main():
                 "kappa": float(np.linalg.norm(k32 - k64) / np.linalg.norm(k64))},
             "after_steps": int(s32),
             "step_hbm_frac": (w32.M * args.steps / el32) * 16 * C * N * 8 / HBM_PEAK}
+
+    if args.batched and args.workload == "cfg2":
+        variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu:

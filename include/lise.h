@@ -61,8 +61,13 @@ typedef struct {
 /* Arithmetic of the state, FFTs and integrator.  Densities, potentials,
  * norms and energies are always accumulated in float64. */
 typedef enum {
-    LISE_FP64 = 0,      /* complex128 state */
-    LISE_FP32 = 1,      /* complex64 state, float64 sums */
+    LISE_FP64 = 0,       /* complex128 state */
+    LISE_FP32 = 1,       /* complex64 state, float64 sums */
+    LISE_FP32_MFMA = 2,  /* as LISE_FP32, with the xy-plane kinetic term as two
+                            dense products with the DVR kinetic matrix on the
+                            matrix cores, operands split into bf16 hi + lo
+                            (three products, float32 accumulation); square
+                            xy-planes of side 16, 32, 48 or 64 only */
 } lise_precision;
 
 /* Functional and Hamiltonian parameters.

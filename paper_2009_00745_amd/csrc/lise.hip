@@ -14,6 +14,8 @@
 #include "lise.h"
 #include "lise_device.hpp"
 #include "lise_fast.hpp"
+#include "lise_mfma.hpp"
+#include <type_traits>
 
 using namespace lise;
 
@@ -103,6 +105,7 @@ struct lise_ctx {
     hipStream_t s2 = nullptr;  // internal stream of the z-axis kernel (default priority)
     hipEvent_t ev_start = nullptr, ev_kz[2] = {nullptr, nullptr}, ev_kp[2] = {nullptr, nullptr};
     int overlap = 1;
+    int mfma_mode = 0;         // precision LISE_FP32_MFMA
     double* dpart = nullptr;   // density partial slots
     int slot_cap = 0;
     double* dens_cur = nullptr;
@@ -125,6 +128,8 @@ struct lise_ctx {
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
     bool fast_xy = false, fast_z = false;   // size-specialised register-FFT kernels
+    bool mfma_xy = false;                   // split-bf16 MFMA plane kernel (LISE_FP32_MFMA)
+    short* dkin = nullptr;                  // bf16 hi/lo of the 1D kinetic matrix
     int tw_full_xy = -1, tw_full_z = -1;    // offsets of W_n^j tables (j < n)
 
     // state
@@ -257,12 +262,61 @@ void set_type_attrs(int lim) {
     for (const void* f : g) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
+template <int NS>
+void set_mfma_attrs(int lim) {
+    (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
 void set_all_attrs(int lim) {
     static bool done = false;
     if (done) return;
     done = true;
     set_type_attrs<double>(lim);
     set_type_attrs<float>(lim);
+    set_mfma_attrs<16>(lim);
+    set_mfma_attrs<32>(lim);
+    set_mfma_attrs<48>(lim);
+    set_mfma_attrs<64>(lim);
+}
+
+bool mfma_side(int n) { return n == 16 || n == 32 || n == 48 || n == 64; }
+
+// float -> bfloat16 bits, round to nearest even (host side)
+unsigned short host_bf16(float f) {
+    unsigned u;
+    std::memcpy(&u, &f, 4);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+float host_bf16_value(unsigned short h) {
+    unsigned u = ((unsigned)h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// bf16 hi/lo parts of the 1D spectral kinetic matrix
+// T[n][m] = (1/N) sum_k (k^2/2) cos(k (n - m) a), k in FFT order.
+std::vector<unsigned short> kinetic_matrix_bf16(int n, double a) {
+    std::vector<unsigned short> out(2 * (size_t)n * n);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    for (int r = 0; r < n; ++r)
+        for (int m = 0; m < n; ++m) {
+            long double acc = 0.0L;
+            for (int j = 0; j < n; ++j) {
+                const int js = (2 * j < n) ? j : j - n;
+                const long double k = 2.0L * pi * js / ((long double)n * a);
+                acc += 0.5L * k * k * cosl(k * (long double)(r - m) * a);
+            }
+            const float v = (float)(acc / n);
+            const unsigned short hi = host_bf16(v);
+            const unsigned short lo = host_bf16(v - host_bf16_value(hi));
+            out[(size_t)r * n + m] = hi;
+            out[(size_t)n * n + (size_t)r * n + m] = lo;
+        }
+    return out;
 }
 
 // Choose launch geometry and (re)allocate scratch for the current tuning.
@@ -272,7 +326,8 @@ int configure(lise_ctx* c) {
     const long long nxy = (long long)nx * ny;
     // fused: the whole cube of one component pair in LDS (two buffers)
     c->fused = false;
-    if (c->fused_pref && kp_lds_bytes(c, nz) <= c->lds_limit && c->N <= 16LL * kThreads) c->fused = true;
+    if (c->fused_pref && !c->mfma_mode && kp_lds_bytes(c, nz) <= c->lds_limit && c->N <= 16LL * kThreads)
+        c->fused = true;
     if (c->fused) {
         c->zb = nz;
     } else {
@@ -291,10 +346,11 @@ int configure(lise_ctx* c) {
         if (kz_lds_bytes(c, yb) > c->lds_limit)
             return fail(c, LISE_E_UNSUPPORTED, "xz-tile does not fit in LDS");
     }
-    c->fast_xy = !c->fused && !c->generic && nx == ny && fast_side(nx) && fast_kp_lds(c) <= c->lds_limit &&
-                 c->tw_full_xy >= 0;
+    c->mfma_xy = c->mfma_mode && !c->fused && nx == ny && mfma_side(nx) && c->dkin;
+    c->fast_xy = !c->mfma_xy && !c->fused && !c->generic && nx == ny && fast_side(nx) &&
+                 fast_kp_lds(c) <= c->lds_limit && c->tw_full_xy >= 0;
     c->fast_z = !c->fused && !c->generic && fast_side(nz) && c->tw_full_z >= 0;
-    if (c->fast_xy) c->zb = 1;
+    if (c->fast_xy || c->mfma_xy) c->zb = 1;
     const long long P = (long long)c->zb * nxy;
     const long long ppt = (P + kThreads - 1) / kThreads;
     if (ppt > 16) return fail(c, LISE_E_UNSUPPORTED, "plane stack of %lld points exceeds 16 per thread", P);
@@ -397,10 +453,32 @@ void launch_kp_fast_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
                        reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
 }
 
+template <int MODE, int NS>
+void launch_kp_mfma_n(lise_ctx* c, const KPArgs<float>& a, dim3 grid) {
+    constexpr int block = mfma_block<NS>();
+    const size_t lds = std::max(kp_mfma_lds<NS>(), (size_t)block * sizeof(double));
+    hipLaunchKernelGGL((kp_mfma<NS, MODE>), grid, dim3(block), lds, c->stream, a, c->dkin);
+}
+
 template <typename T, int MODE>
 int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     a.j0 = j0;
     a.kcount = k;
+    if constexpr (std::is_same<T, float>::value) {
+        if (c->mfma_xy) {
+            dim3 grid(c->lat.nz, (k + c->jg - 1) / c->jg);
+            hipEvent_t ev;
+            prof_begin(c, cls, &ev);
+            switch (c->lat.nx) {
+                case 16: launch_kp_mfma_n<MODE, 16>(c, a, grid); break;
+                case 32: launch_kp_mfma_n<MODE, 32>(c, a, grid); break;
+                case 48: launch_kp_mfma_n<MODE, 48>(c, a, grid); break;
+                default: launch_kp_mfma_n<MODE, 64>(c, a, grid); break;
+            }
+            prof_end(c, cls, ev);
+            return check_launch(c, "kp_mfma");
+        }
+    }
     if (c->fast_xy) {
         dim3 grid(c->lat.nz, (k + c->jg - 1) / c->jg);
         hipEvent_t ev;
@@ -994,10 +1072,13 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
                          lat->nx, lat->ny, lat->nz));
     if (n_qpwf < 1) return bail(fail(c, LISE_E_ARG, "n_qpwf must be >= 1"));
     if (fn->ncomp != 2 && fn->ncomp != 4) return bail(fail(c, LISE_E_ARG, "ncomp must be 2 or 4"));
-    if (fn->precision != LISE_FP64 && fn->precision != LISE_FP32)
+    if (fn->precision != LISE_FP64 && fn->precision != LISE_FP32 && fn->precision != LISE_FP32_MFMA)
         return bail(fail(c, LISE_E_UNSUPPORTED, "precision %d not supported", fn->precision));
+    if (fn->precision == LISE_FP32_MFMA && !(lat->nx == lat->ny && mfma_side(lat->nx)))
+        return bail(fail(c, LISE_E_UNSUPPORTED, "the MFMA form needs square xy-planes of side 16, 32, 48 or 64"));
     c->C = fn->ncomp;
-    c->prec = fn->precision;
+    c->mfma_mode = fn->precision == LISE_FP32_MFMA ? 1 : 0;
+    c->prec = fn->precision == LISE_FP64 ? LISE_FP64 : LISE_FP32;
     c->esz = c->prec == LISE_FP64 ? 16 : 8;
     c->M = n_qpwf;
     c->N = (long long)lat->nx * lat->ny * lat->nz;
@@ -1043,6 +1124,13 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
         e = hipMemcpy(c->tw, tf.data(), tf.size() * sizeof(cpx<float>), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "twiddle upload: %s", hipGetErrorString(e)));
+    if (c->mfma_mode) {
+        const std::vector<unsigned short> dk = kinetic_matrix_bf16(lat->nx, lat->a);
+        int rc0 = dalloc(c, reinterpret_cast<void**>(&c->dkin), dk.size() * sizeof(short));
+        if (rc0) return bail(rc0);
+        e = hipMemcpy(c->dkin, dk.data(), dk.size() * sizeof(short), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "kinetic table upload: %s", hipGetErrorString(e)));
+    }
     const size_t state_bytes = (size_t)c->M * c->per * c->esz;
     for (int i = 0; i < 7; ++i) {
         int rc = dalloc(c, &c->buf[i], state_bytes);
@@ -1461,6 +1549,7 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->bad));
     dfree(reinterpret_cast<void**>(&c->dtime));
+    dfree(reinterpret_cast<void**>(&c->dkin));
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& ev : c->prof.pool) (void)hipEventDestroy(ev);
     delete c;

@@ -202,9 +202,13 @@ __device__ __forceinline__ void lane_inv(cpx<T>* x, const cpx<T>* __restrict__ t
 
 // lanes per line of the plane kernel: enough that a lane holds at most 4
 // points of a line, capped at 16
+#ifndef LISE_PLANE_MAXP_F64
+#define LISE_PLANE_MAXP_F64 4
+#endif
+
 template <typename T, int N>
 constexpr int plane_lanes() {
-    constexpr int maxp = 4;
+    constexpr int maxp = sizeof(T) == 8 ? LISE_PLANE_MAXP_F64 : 4;
     int L = 4;
     while (N / L > maxp && L < 16 && N % (2 * L) == 0) L *= 2;
     return L;

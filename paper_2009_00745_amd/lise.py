@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblise.so")
 
-LISE_FP64, LISE_FP32 = 0, 1
+LISE_FP64, LISE_FP32, LISE_FP32_MFMA = 0, 1, 2
 ERRORS = {0: "OK", -1: "LISE_E_ARG", -2: "LISE_E_NOMEM", -3: "LISE_E_UNSUPPORTED",
           -4: "LISE_E_HIP", -5: "LISE_E_STATE", -6: "LISE_E_NAN"}
 
