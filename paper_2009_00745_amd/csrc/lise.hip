@@ -13,65 +13,22 @@
 
 #include "lise.h"
 #include "lise_device.hpp"
+#define LISE_PLAN_HAVE_DEVICE_TYPES 1
+#include "lise_plan.hpp"
 #include "lise_fast.hpp"
 #include "lise_mfma.hpp"
 #include <type_traits>
 
 using namespace lise;
+using lise::plan::factorize;
+using lise::plan::make_plan;
+using lise::plan::mfma_side;
+using lise::plan::kinetic_matrix_bf16;
 
 namespace {
 
 constexpr int kThreads = 256;
 const char* kVersion = "lise-mi355x 0.1 (gfx950)";
-
-// ---------------------------------------------------------------------------
-// FFT plans
-
-bool factorize(int n, int* radix, int* nst) {
-    if (n < 1) return false;
-    int e2 = 0, m = n;
-    while (m % 2 == 0) { m /= 2; ++e2; }
-    std::vector<int> r;
-    // powers of two: prefer radix 8, then a 4-4 or 4 or 2 remainder
-    int rem = e2;
-    while (rem >= 3 && !(rem == 4)) { r.push_back(8); rem -= 3; }
-    if (rem == 4) { r.push_back(4); r.push_back(4); rem = 0; }
-    if (rem == 2) { r.push_back(4); rem = 0; }
-    if (rem == 1) { r.push_back(2); rem = 0; }
-    while (m % 3 == 0) { r.push_back(3); m /= 3; }
-    while (m % 5 == 0) { r.push_back(5); m /= 5; }
-    if (m != 1) return false;
-    if ((int)r.size() > kMaxStages) return false;
-    *nst = (int)r.size();
-    for (size_t i = 0; i < r.size(); ++i) radix[i] = r[i];
-    return true;
-}
-
-// Build the plan of one axis and append its twiddles (double precision,
-// angles reduced exactly: 2 pi (q k mod (pR)) / (pR)).
-bool make_plan(int n, AxisPlan* pl, std::vector<cpx<double>>* tw) {
-    std::memset(pl, 0, sizeof(*pl));
-    pl->n = n;
-    if (!factorize(n, pl->radix, &pl->nst)) return false;
-    int p = 1;
-    for (int s = 0; s < pl->nst; ++s) {
-        const int R = pl->radix[s];
-        pl->p[s] = p;
-        pl->tw[s] = (int)tw->size();
-        const long long pr = (long long)p * R;
-        for (int k = 0; k < p; ++k)
-            for (int q = 1; q < R; ++q) {
-                const long long num = ((long long)q * k) % pr;
-                const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)num / (long double)pr;
-                cpx<double> w;
-                w.re = (double)cosl(ang);
-                w.im = (double)sinl(ang);
-                tw->push_back(w);
-            }
-        p *= R;
-    }
-    return true;
-}
 
 struct Prof {
     bool on = false;
@@ -280,43 +237,6 @@ void set_all_attrs(int lim) {
     set_mfma_attrs<32>(lim);
     set_mfma_attrs<48>(lim);
     set_mfma_attrs<64>(lim);
-}
-
-bool mfma_side(int n) { return n == 16 || n == 32 || n == 48 || n == 64; }
-
-// float -> bfloat16 bits, round to nearest even (host side)
-unsigned short host_bf16(float f) {
-    unsigned u;
-    std::memcpy(&u, &f, 4);
-    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-float host_bf16_value(unsigned short h) {
-    unsigned u = ((unsigned)h) << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
-// bf16 hi/lo parts of the 1D spectral kinetic matrix
-// T[n][m] = (1/N) sum_k (k^2/2) cos(k (n - m) a), k in FFT order.
-std::vector<unsigned short> kinetic_matrix_bf16(int n, double a) {
-    std::vector<unsigned short> out(2 * (size_t)n * n);
-    const long double pi = 3.14159265358979323846264338327950288L;
-    for (int r = 0; r < n; ++r)
-        for (int m = 0; m < n; ++m) {
-            long double acc = 0.0L;
-            for (int j = 0; j < n; ++j) {
-                const int js = (2 * j < n) ? j : j - n;
-                const long double k = 2.0L * pi * js / ((long double)n * a);
-                acc += 0.5L * k * k * cosl(k * (long double)(r - m) * a);
-            }
-            const float v = (float)(acc / n);
-            const unsigned short hi = host_bf16(v);
-            const unsigned short lo = host_bf16(v - host_bf16_value(hi));
-            out[(size_t)r * n + m] = hi;
-            out[(size_t)n * n + (size_t)r * n + m] = lo;
-        }
-    return out;
 }
 
 // Choose launch geometry and (re)allocate scratch for the current tuning.
@@ -1096,17 +1016,7 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     if (!make_plan(lat->nx, &c->px, &tw) || !make_plan(lat->ny, &c->py, &tw) || !make_plan(lat->nz, &c->pz, &tw))
         return bail(fail(c, LISE_E_UNSUPPORTED, "no FFT plan"));
     // W_n^j tables (j < n) for the register-FFT kernels
-    auto full_table = [&](int n) {
-        const int off = (int)tw.size();
-        for (int j = 0; j < n; ++j) {
-            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
-            cpx<double> w;
-            w.re = (double)cosl(ang);
-            w.im = (double)sinl(ang);
-            tw.push_back(w);
-        }
-        return off;
-    };
+    auto full_table = [&](int n) { return plan::full_table(n, &tw); };
     if (lat->nx == lat->ny && fast_side(lat->nx)) c->tw_full_xy = full_table(lat->nx);
     if (fast_side(lat->nz)) c->tw_full_z = full_table(lat->nz);
     if (c->prec == LISE_FP64) {

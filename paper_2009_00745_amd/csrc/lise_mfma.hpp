@@ -11,7 +11,8 @@
 // term, ~2^-16 relative, is dropped).  The z term comes from the register FFT
 // kernel as in the other forms.
 //
-// v_mfma_f32_16x16x16bf16_1k, one 64-lane wave per 16 x 16 output tile:
+// v_mfma_f32_16x16x16bf16_1k, one 64-lane wave per 16 x 16 output tile
+// (two tiles of one tile-row for the 64 x 64 plane):
 //   A[i][k]: lane l holds i = l % 16, k = 4 (l / 16) + t, t < 4
 //   B[k][j]: lane l holds j = l % 16, k = 4 (l / 16) + t
 //   D[i][j]: lane l, register r holds i = 4 (l / 16) + r, j = l % 16
@@ -45,9 +46,16 @@ __device__ __forceinline__ f32x4 mfma3(bf16x4 ah, bf16x4 al, bf16x4 bh, bf16x4 b
     return c;
 }
 
+// output tiles per wave (two tiles of one tile-row for the 64 x 64 plane, so
+// that a workgroup has at most 8 waves and a wave may use 256 registers)
+template <int N>
+constexpr int mfma_tpw() {
+    return N >= 64 ? 2 : 1;
+}
+
 template <int N>
 constexpr int mfma_block() {
-    return 64 * (N / 16) * (N / 16);
+    return 64 * (N / 16) * (N / 16) / mfma_tpw<N>();
 }
 
 template <int N>
@@ -60,6 +68,7 @@ template <int N, int MODE>
 __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float> a,
                                                             const short* __restrict__ Dhl) {
     constexpr int NT = N / 16;
+    constexpr int TPW = mfma_tpw<N>();
     constexpr int LD = N + 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<float>* Fa = reinterpret_cast<cpx<float>*>(smem_raw);
@@ -69,7 +78,7 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int ty = wave / NT, tx = wave % NT;
+    const int ty = wave / (NT / TPW), tx0 = (wave % (NT / TPW)) * TPW;
     const int li = lane & 15, lk = 4 * (lane >> 4);
     const int z = blockIdx.x;
     constexpr long long nxy = (long long)N * N;
@@ -78,9 +87,9 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
     const int jend = min(a.kcount, jbeg + a.jg);
     const float cdt = float(a.dt / 48.0);
     const cpx<float> coef = mk(float(a.coef_re), float(a.coef_im));
-    double dn[4], dkr[4], dki[4];
+    double dn[4 * TPW], dkr[4 * TPW], dki[4 * TPW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dn[r] = dkr[r] = dki[r] = 0.0;
+    for (int r = 0; r < 4 * TPW; ++r) dn[r] = dkr[r] = dki[r] = 0.0;
     double ekin = 0.0;
 
     for (int jl = jbeg; jl < jend; ++jl) {
@@ -94,10 +103,13 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
                 Fb[y * LD + x] = a.in[offb + e];
             }
             __syncthreads();
-            f32x4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0}, br = {0, 0, 0, 0}, bi = {0, 0, 0, 0};
+            f32x4 ar[TPW], ai[TPW], br[TPW], bi[TPW];
 #pragma unroll
+            for (int u = 0; u < TPW; ++u) ar[u] = ai[u] = br[u] = bi[u] = f32x4{0, 0, 0, 0};
+#pragma unroll 1
             for (int kk = 0; kk < NT; ++kk) {
-                // x product: C[y][x] += sum_k F[y][k] T[k][x]
+                // x product: C[y][x] += sum_k F[y][k] T[k][x]; the F fragment
+                // (rows of tile-row ty) is shared by the wave's tiles
                 bf16x4 far_h, far_l, fai_h, fai_l, fbr_h, fbr_l, fbi_h, fbi_l, d_h, d_l;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -108,44 +120,64 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
                     split_bf16(u.im, fai_h, fai_l, t);
                     split_bf16(v.re, fbr_h, fbr_l, t);
                     split_bf16(v.im, fbi_h, fbi_l, t);
-                    d_h[t] = Dh[k * N + 16 * tx + li];
-                    d_l[t] = Dl[k * N + 16 * tx + li];
                 }
-                ar = mfma3(far_h, far_l, d_h, d_l, ar);
-                ai = mfma3(fai_h, fai_l, d_h, d_l, ai);
-                br = mfma3(fbr_h, fbr_l, d_h, d_l, br);
-                bi = mfma3(fbi_h, fbi_l, d_h, d_l, bi);
-                // y product: C[y][x] += sum_k T[y][k] F[k][x]
+#pragma unroll
+                for (int u = 0; u < TPW; ++u) {
+                    const int tx = tx0 + u;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = 16 * kk + lk + t;
+                        d_h[t] = Dh[k * N + 16 * tx + li];
+                        d_l[t] = Dl[k * N + 16 * tx + li];
+                    }
+                    ar[u] = mfma3(far_h, far_l, d_h, d_l, ar[u]);
+                    ai[u] = mfma3(fai_h, fai_l, d_h, d_l, ai[u]);
+                    br[u] = mfma3(fbr_h, fbr_l, d_h, d_l, br[u]);
+                    bi[u] = mfma3(fbi_h, fbi_l, d_h, d_l, bi[u]);
+                }
+                // y product: C[y][x] += sum_k T[y][k] F[k][x]; the T fragment is shared
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = 16 * kk + lk + t;
                     d_h[t] = Dh[(16 * ty + li) * N + k];
                     d_l[t] = Dl[(16 * ty + li) * N + k];
-                    const cpx<float> u = Fa[k * LD + 16 * tx + li];
-                    const cpx<float> v = Fb[k * LD + 16 * tx + li];
-                    split_bf16(u.re, far_h, far_l, t);
-                    split_bf16(u.im, fai_h, fai_l, t);
-                    split_bf16(v.re, fbr_h, fbr_l, t);
-                    split_bf16(v.im, fbi_h, fbi_l, t);
                 }
-                ar = mfma3(d_h, d_l, far_h, far_l, ar);
-                ai = mfma3(d_h, d_l, fai_h, fai_l, ai);
-                br = mfma3(d_h, d_l, fbr_h, fbr_l, br);
-                bi = mfma3(d_h, d_l, fbi_h, fbi_l, bi);
+#pragma unroll
+                for (int u = 0; u < TPW; ++u) {
+                    const int tx = tx0 + u;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int k = 16 * kk + lk + t;
+                        const cpx<float> uu = Fa[k * LD + 16 * tx + li];
+                        const cpx<float> vv = Fb[k * LD + 16 * tx + li];
+                        split_bf16(uu.re, far_h, far_l, t);
+                        split_bf16(uu.im, fai_h, fai_l, t);
+                        split_bf16(vv.re, fbr_h, fbr_l, t);
+                        split_bf16(vv.im, fbi_h, fbi_l, t);
+                    }
+                    ar[u] = mfma3(d_h, d_l, far_h, far_l, ar[u]);
+                    ai[u] = mfma3(d_h, d_l, fai_h, fai_l, ai[u]);
+                    br[u] = mfma3(d_h, d_l, fbr_h, fbr_l, br[u]);
+                    bi[u] = mfma3(d_h, d_l, fbi_h, fbi_l, bi[u]);
+                }
             }
             const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z) * nxy;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int y = 16 * ty + lk + r, x = 16 * tx + li;
-                const int pt = y * N + x;
-                cpx<float> Ta = mk(ar[r], ai[r]), Tb = mk(br[r], bi[r]);
-                if (!a.fused) {
-                    Ta = Ta + a.G[lofa + pt];
-                    Tb = Tb + a.G[lofb + pt];
+            for (int u = 0; u < TPW; ++u) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int y = 16 * ty + lk + r, x = 16 * (tx0 + u) + li;
+                    const int pt = y * N + x;
+                    cpx<float> Ta = mk(ar[u][r], ai[u][r]), Tb = mk(br[u][r], bi[u][r]);
+                    if (!a.fused) {
+                        Ta = Ta + a.G[lofa + pt];
+                        Tb = Tb + a.G[lofb + pt];
+                    }
+                    point_epilogue<float, MODE>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt, offb + pt,
+                                                (long long)z * nxy + pt, coef, cdt, dn[u * 4 + r], dkr[u * 4 + r],
+                                                dki[u * 4 + r], ekin);
                 }
-                point_epilogue<float, MODE>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt, offb + pt,
-                                            (long long)z * nxy + pt, coef, cdt, dn[r], dkr[r], dki[r], ekin);
             }
             __syncthreads();
         }
@@ -166,18 +198,21 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
     if (a.dens_src) {
         double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pt = (16 * ty + lk + r) * N + 16 * tx + li;
-            if (a.accumulate) {
-                base[pt] += dn[r];
-                base[N3 + pt] += dkr[r];
-                base[2 * N3 + pt] += dki[r];
-            } else {
-                base[pt] = dn[r];
-                base[N3 + pt] = dkr[r];
-                base[2 * N3 + pt] = dki[r];
+        for (int u = 0; u < TPW; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = (16 * ty + lk + r) * N + 16 * (tx0 + u) + li;
+                const int i = u * 4 + r;
+                if (a.accumulate) {
+                    base[pt] += dn[i];
+                    base[N3 + pt] += dkr[i];
+                    base[2 * N3 + pt] += dki[i];
+                } else {
+                    base[pt] = dn[i];
+                    base[N3 + pt] = dkr[i];
+                    base[2 * N3 + pt] = dki[i];
+                }
             }
-        }
     }
 }
 
