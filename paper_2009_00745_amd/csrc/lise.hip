@@ -640,7 +640,7 @@ int abm_step_t(lise_ctx* c) {
     const int d2 = 2 + (c->dn + 2) % 4;         // y'_{n-2}
     const int d3 = 2 + (c->dn + 1) % 4;         // y'_{n-3}, then m
     const int yn = c->iy, ym1 = 1 - c->iy;
-    // phase 1: H y_n -> y'_n, m, X, Y; densities of m
+    // phase 1: H y_n -> y'_n, m, Y; densities of m
     {
         KPArgs<T> a = kp_base<T>(c);
         a.V = c->V_cur;
@@ -666,7 +666,7 @@ int abm_step_t(lise_ctx* c) {
         a.in = S<T>(c, d3);                         // m
         a.G = reinterpret_cast<const cpx<T>*>(c->G);
         a.a1 = S<T>(c, ym1);                        // Y -> y_{n+1}
-        a.a5 = S<T>(c, 6);                          // X -> p_{n+1} - c_{n+1}
+        a.a5 = S<T>(c, 6);                          // p_n - c_n -> p_{n+1} - c_{n+1}
         a.dt = dt;
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0)));

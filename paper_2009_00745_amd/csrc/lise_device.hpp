@@ -256,8 +256,8 @@ struct KPArgs {
     int acc_from_in;
     double coef_re, coef_im;
     // KP_ABM1: in = y_n, a1 = y_{n-1} -> Y, a2 = y'_{n-1}, a3 = y'_{n-2},
-    //          a4 = y'_{n-3} -> m, a5 = p_n - c_n -> X, a6 -> y'_n
-    // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = X -> p_{n+1} - c_{n+1}
+    //          a4 = y'_{n-3} -> m, a5 = p_n - c_n (read only), a6 -> y'_n
+    // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = p_n - c_n -> p_{n+1} - c_{n+1}
     cpx<T>* a1;
     cpx<T>* a2;
     cpx<T>* a3;
@@ -277,19 +277,20 @@ struct KPArgs {
 // float64 density accumulation of the vector the mode produces.
 //
 // The ABM phases use an exact re-association of Eq. (p), (m), (c), (y) that
-// lets phase 2 read only m, X, Y (and the z-term G):
+// lets phase 2 read only m, Y, d_n = p_n - c_n (and the z-term G):
 //   phase 1: s = (y_n + y_{n-1})/2,
 //            c~ = s + dt/48 (51 y'_n + 3 y'_{n-1} + y'_{n-2})   (c without m'),
 //            Y = p - c~ = dt/48 (68 y'_n - 102 y'_{n-1} + 68 y'_{n-2} - 17 y'_{n-3}),
-//            p = c~ + Y, m = p - 161/170 (p_n - c_n), X = c~ + 9/170 Y;
+//            m = c~ + Y - 161/170 d_n   (= p - 161/170 d_n);
 //   phase 2: with k = 17 dt / 48 and m' = -i H m,
-//            y_{n+1} = c + 9/170 (p - c) = X + 161/170 k m',
-//            p_{n+1} - c_{n+1} = p - c = Y - k m'.
-// Y is formed from the derivatives directly and X as c~ plus a multiple of Y,
-// so no quantity of the size of y is cancelled and, in float32, the weights
-// of the final combination add up to one exactly.
-// Phase 1 stores y'_n over y'_{n-4}, m over y'_{n-3}, X over p_n - c_n and Y
-// over y_{n-1}; phase 2 stores y_{n+1} over Y and p_{n+1} - c_{n+1} over X.
+//            d_{n+1} = p - c = Y - k m',
+//            y_{n+1} = c + 9/170 (p - c) = p - 161/170 d_{n+1}
+//                    = m + 161/170 (d_n - d_{n+1}).
+// Y is formed from the derivatives directly and y_{n+1} as m plus a small
+// correction, so no quantity of the size of y is cancelled and no float32
+// weights have to add up to one.  Phase 1 stores y'_n over y'_{n-4}, m over
+// y'_{n-3} and Y over y_{n-1} (d_n stays); phase 2 stores y_{n+1} over Y and
+// d_{n+1} over d_n.
 
 template <typename T, int MODE>
 __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
@@ -337,22 +338,20 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
         const cpx<T> Yb = cdt * (T(68) * db - T(102) * d1b + T(68) * d2b - T(17) * d3b);
         const cpx<T> ca = sa + cdt * (T(51) * da + T(3) * d1a + d2a);
         const cpx<T> cb = sb + cdt * (T(51) * db + T(3) * d1b + d2b);
-        va = (ca + Ya) - T(161.0 / 170.0) * a.a5[ea];   // m = p - 161/170 (p_n - c_n)
+        va = (ca + Ya) - T(161.0 / 170.0) * a.a5[ea];   // m = p - 161/170 d_n
         vb = (cb + Yb) - T(161.0 / 170.0) * a.a5[eb];
         a.a6[ea] = da;
         a.a6[eb] = db;
         a.a4[ea] = va;
         a.a4[eb] = vb;
-        a.a5[ea] = ca + T(9.0 / 170.0) * Ya;
-        a.a5[eb] = cb + T(9.0 / 170.0) * Yb;
         a.a1[ea] = Ya;
         a.a1[eb] = Yb;
-    } else {   // KP_ABM2: in = m, a5 = X -> p_{n+1} - c_{n+1}, a1 = Y -> y_{n+1}
+    } else {   // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = d_n -> d_{n+1}
         const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
         const T k = T(17) * cdt;
-        va = a.a5[ea] + (T(161.0 / 170.0) * k) * ma;
-        vb = a.a5[eb] + (T(161.0 / 170.0) * k) * mb;
-        const cpx<T> ra = a.a1[ea] - k * ma, rb = a.a1[eb] - k * mb;
+        const cpx<T> ra = a.a1[ea] - k * ma, rb = a.a1[eb] - k * mb;   // d_{n+1}
+        va = fa + T(161.0 / 170.0) * (a.a5[ea] - ra);                    // y_{n+1}
+        vb = fb + T(161.0 / 170.0) * (a.a5[eb] - rb);
         a.a1[ea] = va;
         a.a1[eb] = vb;
         a.a5[ea] = ra;

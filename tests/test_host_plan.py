@@ -94,7 +94,6 @@ def test_full_tables(hp, n):
     assert hp.hp_full_table(n, tw.ctypes.data_as(ct.c_void_p)) == n
     w = tw[0::2] + 1j * tw[1::2]
     # reference in 80-bit long double (numpy's float64 angle 2 pi j / n is itself off by ~1e-15)
-    ang = -2 * np.pi * np.arange(n, dtype=np.longdouble) / np.longdouble(n)
     ang = -2 * np.longdouble("3.14159265358979323846264338327950288") * np.arange(n, dtype=np.longdouble) / n
     ref = np.cos(ang).astype(np.float64) + 1j * np.sin(ang).astype(np.float64)
     assert np.max(np.abs(w - ref)) < 1.2e-16
