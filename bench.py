@@ -52,7 +52,7 @@ def upload(ctx, w, piece=512):
         ctx.set_qpwf(j0, np.ascontiguousarray(w.qpwfs(j0, k)))
 
 
-def run_gpu(w, steps, warmup, tuning=None, profile=True):
+def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     import torch
     import paper_2009_00745_amd as lise
     stream = torch.cuda.current_stream().cuda_stream
@@ -63,6 +63,11 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True):
     upload(ctx, w)
     log(f"{w.name}: uploaded {w.M} qpwfs in {time.time() - t0:.1f}s, device memory {ctx.memory() / 2**30:.1f} GiB")
     ctx.startup(w.dt)
+    chosen = None
+    if autotune:
+        t0 = time.time()
+        chosen = ctx.autotune(w.dt, 2)
+        log(f"{w.name}: autotune picked {chosen} in {time.time() - t0:.1f}s")
     if warmup:
         ctx.step(w.dt, warmup)
     torch.cuda.synchronize()
@@ -80,12 +85,13 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True):
             prof[name] = ctx.profile_read(cls)
         ctx.profile(0)
     log(f"{w.name}: {steps} steps in {t2 - t1:.3f}s")
+    prof["tuning"] = chosen
     return ctx, t2 - t1, prof
 
 
 def run_batched(nsys, steps, warmup):
-    """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced by one
-    graph launch per four ABM steps, each system on its own graph branch."""
+    """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced together,
+    each on its own forked stream with its own four-step graph replays."""
     import torch
     import workloads as wl
     import paper_2009_00745_amd as lise
@@ -167,6 +173,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batched", type=int, default=16,
                     help="number of independent systems in the batched variant (0 = skip; 64 = full workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -202,7 +209,9 @@ def main():
         tuning = {"chunk_qpwf": args.chunk, "jgroup": args.jgroup}
     C, N = w.functional.ncomp, w.lattice.n
     esz = 16 if w.functional.precision == 0 else 8
-    ctx, elapsed, prof = run_gpu(w, args.steps, args.warmup, tuning)
+    autotune = not args.no_autotune and not tuning
+    ctx, elapsed, prof = run_gpu(w, args.steps, args.warmup, tuning, autotune=autotune)
+    chosen = prof.pop("tuning")
     value = w.M * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
     b_alg = 16 * C * N * esz                      # compulsory state bytes per qpwf-step
@@ -218,6 +227,8 @@ def main():
                 "avg_launch_ms": ms_plane / n_plane,
                 "alg_bytes_per_launch": alg_bytes_total / n_plane}
     breakdown = {k: {"launches": n, "ms_per_step": ms / args.steps} for k, (n, ms) in prof.items()}
+    if chosen:
+        tuning = {"autotuned": chosen}
     t_now, s_now = ctx.time()
     n64, k64 = ctx.densities()
     obs = ctx.observables()
@@ -228,11 +239,13 @@ def main():
     variants = {}
     if not args.no_fp32 and args.workload == "cfg2":
         w32 = make_workload("cfg2_fp32", M=args.M)
-        ctx32, el32, prof32 = run_gpu(w32, args.steps, args.warmup, tuning)
+        ctx32, el32, prof32 = run_gpu(w32, args.steps, args.warmup, tuning if not autotune else None,
+                                      autotune=autotune)
+        chosen32 = prof32.pop("tuning")
         n32, k32 = ctx32.densities()
         t32, s32 = ctx32.time()
         ctx32.close()
-        assert s32 == s_now
+        assert s32 == s_now, (s32, s_now)
         variants["fp32_same_workload"] = {
             "value": w32.M * args.steps / el32, "unit": "qpwf-steps/s",
             "ms_per_step": 1e3 * el32 / args.steps,
@@ -242,6 +255,7 @@ def main():
                 "n": float(np.linalg.norm(n32 - n64) / np.linalg.norm(n64)),
                 "kappa": float(np.linalg.norm(k32 - k64) / np.linalg.norm(k64))},
             "after_steps": int(s32),
+            "tuning": chosen32,
             "step_hbm_frac": (w32.M * args.steps / el32) * 16 * C * N * 8 / HBM_PEAK}
 
     if args.batched and args.workload == "cfg2":

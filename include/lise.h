@@ -222,11 +222,13 @@ int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chos
  * counts) advanced together.  lise_batch_create takes nsys distinct contexts
  * on the current device and moves all of them onto `hip_stream`; the
  * contexts stay owned by the caller and usable (densities, observables) but
- * must not be freed before the batch.  lise_batch_step runs each system's
- * start-up if needed, then captures kPeriod = 4 ABM steps of every system
- * into one HIP graph with one branch per system (branches run concurrently)
- * and replays it; leftover steps run eagerly.  The graph is re-captured when
- * dt, the tuning, or a system's ring of buffers changed since the capture.
+ * must not be freed before the batch.  lise_batch_step forks one internal
+ * stream per system from `hip_stream`, advances every system by nsteps ABM
+ * steps on its own stream (start-up first if needed; with graphs enabled in
+ * the system's tuning, its four-step graph replays as in lise_step), joins
+ * the streams back into `hip_stream` and returns after all systems finished.
+ * The systems' kernels run concurrently on the device.  Results equal
+ * lise_step on each system alone, bit for bit.
  * Errors: ARG, STATE, HIP, NAN (text from lise_batch_last_error). */
 typedef struct lise_batch lise_batch;
 int lise_batch_create(lise_batch **out, int32_t nsys, lise_ctx *const *ctxs, void *hip_stream);

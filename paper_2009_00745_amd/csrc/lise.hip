@@ -60,6 +60,8 @@ struct lise_ctx {
     void* Gbuf[2] = {nullptr, nullptr};   // double buffer when the z kernel runs ahead
     long long g_cap = 0;       // qpwfs each G buffer holds
     hipStream_t s2 = nullptr;  // internal stream of the z-axis kernel (default priority)
+    hipStream_t cap = nullptr; // internal stream graphs are captured on (never the null stream)
+    hipEvent_t ev_cap = nullptr;
     hipEvent_t ev_start = nullptr, ev_kz[2] = {nullptr, nullptr}, ev_kp[2] = {nullptr, nullptr};
     int overlap = 1;
     int mfma_mode = 0;         // precision LISE_FP32_MFMA
@@ -725,10 +727,17 @@ int ensure_graph(lise_ctx* c) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
+    // capture on the internal stream (the caller's stream may be the null
+    // stream, which cannot be captured); it starts after the caller's work
+    HIPCHK(c, hipEventRecord(c->ev_cap, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->cap, c->ev_cap, 0));
+    hipStream_t user = c->stream;
     hipGraph_t g = nullptr;
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap;
     int rc = capture_period(c);
-    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->stream = user;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
     if (rc != LISE_OK) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -741,8 +750,10 @@ int ensure_graph(lise_ctx* c) {
     return LISE_OK;
 }
 
+// Enqueue nsteps ABM steps (start-up first when needed) on the context
+// stream without waiting for them.
 template <typename T>
-int step_t(lise_ctx* c, double dt, long long nsteps) {
+int advance_t(lise_ctx* c, double dt, long long nsteps) {
     if (!c->hist || c->dt_hist != dt) {
         CHK(startup_t<T>(c, dt));
         if (c->gexec) {
@@ -758,6 +769,16 @@ int step_t(lise_ctx* c, double dt, long long nsteps) {
         }
     }
     for (long long s = 0; s < nsteps; ++s) CHK(abm_step_t<T>(c));
+    return LISE_OK;
+}
+
+int advance_any(lise_ctx* c, double dt, long long nsteps) {
+    return c->prec == LISE_FP64 ? advance_t<double>(c, dt, nsteps) : advance_t<float>(c, dt, nsteps);
+}
+
+template <typename T>
+int step_t(lise_ctx* c, double dt, long long nsteps) {
+    CHK(advance_t<T>(c, dt, nsteps));
     return check_bad(c);
 }
 
@@ -906,17 +927,16 @@ int valid_dim(int n) {
 
 }  // namespace
 
-// A batch of independent systems advanced together: one graph launch runs
-// kPeriod ABM steps of every system, each system on its own branch.
+// A batch of independent systems advanced together.  Each system runs on a
+// stream of its own (forked from the caller's stream and joined back), so
+// the systems' kernels overlap on the device; within a system the usual
+// four-step graph replays apply.
 struct lise_batch {
     std::vector<lise_ctx*> sys;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // caller's stream (may be the null stream)
     std::vector<hipStream_t> fork;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
-    hipGraphExec_t gexec = nullptr;
-    std::vector<long long> gsig;
-    double gdt = 0.0;
     char err[512] = {0};
 };
 
@@ -928,43 +948,6 @@ int bfail(lise_batch* b, int code, const char* fmt, ...) {
     vsnprintf(b->err, sizeof(b->err), fmt, ap);
     va_end(ap);
     return code;
-}
-
-int batch_capture(lise_batch* b) {
-    if (b->gexec) {
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-    }
-    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "begin capture: %s", hipGetErrorString(e));
-    int rc = LISE_OK;
-    e = hipEventRecord(b->ev_fork, b->stream);
-    for (size_t i = 0; i < b->sys.size() && rc == LISE_OK && e == hipSuccess; ++i) {
-        lise_ctx* c = b->sys[i];
-        e = hipStreamWaitEvent(b->fork[i], b->ev_fork, 0);
-        if (e != hipSuccess) break;
-        c->stream = b->fork[i];
-        rc = capture_period(c);
-        c->stream = b->stream;
-        if (rc != LISE_OK) {
-            bfail(b, rc, "system %zu: %s", i, c->err);
-            break;
-        }
-        e = hipEventRecord(b->ev_join[i], b->fork[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[i], 0);
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
-    if (rc != LISE_OK || e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        if (rc != LISE_OK) return rc;
-        return bfail(b, LISE_E_HIP, "batch capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-    }
-    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "batch graph instantiation: %s", hipGetErrorString(e));
-    for (size_t i = 0; i < b->sys.size(); ++i) b->gsig[i] = ring_sig(b->sys[i]);
-    return LISE_OK;
 }
 
 }  // namespace
@@ -1063,6 +1046,8 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     if (e == hipSuccess) e = hipMemset(c->bad, 0, sizeof(int));
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipMemset: %s", hipGetErrorString(e)));
     e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_cap, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_start, hipEventDisableTiming);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipEventCreateWithFlags(&c->ev_kz[i], hipEventDisableTiming);
@@ -1299,10 +1284,9 @@ int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, voi
             }
         b->sys.push_back(ctxs[i]);
     }
-    hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     b->fork.assign(nsys, nullptr);
     b->ev_join.assign(nsys, nullptr);
-    b->gsig.assign(nsys, -1);
+    hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
     for (int i = 0; i < nsys && e == hipSuccess; ++i) {
         e = hipStreamCreateWithFlags(&b->fork[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming);
@@ -1311,7 +1295,7 @@ int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, voi
         lise_batch_free(b);
         return LISE_E_HIP;
     }
-    // every system now enqueues on the batch stream
+    // earlier work of every system completes before the batch takes it over
     for (lise_ctx* c : b->sys) {
         (void)hipStreamSynchronize(c->stream);
         c->stream = b->stream;
@@ -1323,40 +1307,40 @@ int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, voi
 int lise_batch_step(lise_batch* b, double dt, int64_t nsteps) {
     if (!b) return LISE_E_ARG;
     if (!std::isfinite(dt) || dt == 0.0 || nsteps < 0) return bfail(b, LISE_E_ARG, "bad dt or nsteps");
-    for (size_t i = 0; i < b->sys.size(); ++i) {
+    for (size_t i = 0; i < b->sys.size(); ++i)
+        if (b->sys[i]->n_set < b->sys[i]->M) return bfail(b, LISE_E_STATE, "system %zu: qpwfs not fully set", i);
+    // fork: every system stream starts after the caller's earlier work
+    hipError_t ef = hipEventRecord(b->ev_fork, b->stream);
+    if (ef != hipSuccess) return bfail(b, LISE_E_HIP, "fork: %s", hipGetErrorString(ef));
+    int rc = LISE_OK;
+    size_t i = 0;
+    for (; i < b->sys.size(); ++i) {
         lise_ctx* c = b->sys[i];
+        hipError_t e = hipStreamWaitEvent(b->fork[i], b->ev_fork, 0);
+        if (e != hipSuccess) {
+            rc = bfail(b, LISE_E_HIP, "fork of system %zu: %s", i, hipGetErrorString(e));
+            break;
+        }
+        c->stream = b->fork[i];
+        rc = advance_any(c, dt, nsteps);
+        if (rc != LISE_OK) {
+            bfail(b, rc, "system %zu: %s", i, c->err);
+            ++i;
+            break;
+        }
+    }
+    // join every forked stream back into the caller's stream, also on failure
+    for (size_t k = 0; k < i; ++k) {
+        lise_ctx* c = b->sys[k];
+        hipError_t e = hipEventRecord(b->ev_join[k], b->fork[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[k], 0);
         c->stream = b->stream;
-        if (c->n_set < c->M) return bfail(b, LISE_E_STATE, "system %zu: qpwfs not fully set", i);
-        if (!c->hist || c->dt_hist != dt) {
-            int rc = c->prec == LISE_FP64 ? startup_t<double>(c, dt) : startup_t<float>(c, dt);
-            if (rc != LISE_OK) return bfail(b, rc, "system %zu start-up: %s", i, c->err);
-        }
+        if (e != hipSuccess && rc == LISE_OK) rc = bfail(b, LISE_E_HIP, "join of system %zu: %s", k, hipGetErrorString(e));
     }
-    if (nsteps >= kPeriod) {
-        bool stale = !b->gexec || b->gdt != dt;
-        for (size_t i = 0; i < b->sys.size() && !stale; ++i) stale = b->gsig[i] != ring_sig(b->sys[i]);
-        if (stale) {
-            int rc = batch_capture(b);
-            if (rc != LISE_OK) return rc;
-            b->gdt = dt;
-        }
-        for (; nsteps >= kPeriod; nsteps -= kPeriod) {
-            hipError_t e = hipGraphLaunch(b->gexec, b->stream);
-            if (e != hipSuccess) return bfail(b, LISE_E_HIP, "graph launch: %s", hipGetErrorString(e));
-            for (lise_ctx* c : b->sys)
-                for (int i = 0; i < kPeriod; ++i) advance_host(c, dt);
-        }
-    }
-    for (size_t i = 0; i < b->sys.size(); ++i) {
-        lise_ctx* c = b->sys[i];
-        for (long long s = 0; s < nsteps; ++s) {
-            int rc = abm_step_any(c);
-            if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", i, c->err);
-        }
-    }
-    for (size_t i = 0; i < b->sys.size(); ++i) {
-        int rc = check_bad(b->sys[i]);
-        if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", i, b->sys[i]->err);
+    if (rc != LISE_OK) return rc;
+    for (size_t k = 0; k < b->sys.size(); ++k) {
+        rc = check_bad(b->sys[k]);
+        if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", k, b->sys[k]->err);
     }
     return LISE_OK;
 }
@@ -1367,7 +1351,8 @@ void lise_batch_free(lise_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
-    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (hipStream_t s : b->fork)
+        if (s) (void)hipStreamSynchronize(s);
     for (hipStream_t s : b->fork)
         if (s) (void)hipStreamDestroy(s);
     for (hipEvent_t e : b->ev_join)
@@ -1441,6 +1426,8 @@ void lise_free(lise_ctx* c) {
     dfree(&c->Gbuf[1]);
     c->G = nullptr;
     if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->ev_cap) (void)hipEventDestroy(c->ev_cap);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     for (int i = 0; i < 2; ++i) {
         if (c->ev_kz[i]) (void)hipEventDestroy(c->ev_kz[i]);

@@ -1,0 +1,98 @@
+"""Full-size parity for the benchmark workload (32^3, 8192 qpwfs, FP64), in the launch
+configuration bench.py times: sampled outputs against the oracle, properties at size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lise():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    import paper_2009_00745_amd as lise_mod
+    lise_mod.load_library()
+    return lise_mod
+
+
+def upload(ctx, w, piece=1024):
+    for j0 in range(0, w.M, piece):
+        ctx.set_qpwf(j0, np.ascontiguousarray(w.qpwfs(j0, min(piece, w.M - j0))))
+
+
+def oracle_densities_chunked(w, piece=512):
+    n = np.zeros((w.lattice.nz, w.lattice.ny, w.lattice.nx))
+    k = np.zeros_like(n, dtype=complex)
+    for j0 in range(0, w.M, piece):
+        dn, dk = oracle.densities(w.qpwfs(j0, min(piece, w.M - j0)), w.functional)
+        n += dn
+        k += dk
+    return n, k
+
+
+def test_config2_full_size(lise):
+    w = wl.config2()
+    say(f"full size {w.name}: upload")
+    ctx = lise.Context(w.lattice, w.M, w.functional)
+    upload(ctx, w)
+    n, k = ctx.densities()
+    n0, k0 = oracle_densities_chunked(w)
+    say(f"  densities rel max err n {np.max(abs(n - n0)) / np.max(abs(n0)):.2e}")
+    assert np.max(np.abs(n - n0)) < 1e-13 * np.max(np.abs(n0))
+    assert np.max(np.abs(k - k0)) < 1e-13 * np.max(np.abs(k0))
+    # sampled H psi with the fields of the whole state
+    V, D = oracle.potentials(n0, k0, w.lattice, w.functional, 0.0)
+    for j in (0, 1, 777, 4096, w.M - 1):
+        got = ctx.apply_h(j, 1)
+        ref = oracle.apply_h(w.qpwfs(j, 1), V, D, w.lattice, w.functional)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        say(f"  apply_h qpwf {j}: rel max err {err:.2e}")
+        assert err < 1e-12
+    o0 = ctx.observables()
+    say("  start-up + 6 ABM steps")
+    ctx.step(w.dt, 6)
+    o1 = ctx.observables()
+    say(f"  norm drift {o1['norm_drift_max']:.2e}, dN {o1['N'] - o0['N']:.2e}")
+    assert o1["norm_drift_max"] < 1e-11
+    assert abs(o1["N"] - o0["N"]) < 1e-9 * o0["N"]
+    # sampled step check: one more step of the GPU state against the oracle's apply-H
+    # of the same sampled qpwfs is covered by the reduced-size step tests; here the
+    # GPU step must also agree with a second GPU run in a different launch shape
+    psi = ctx.get_qpwf(0, 64)
+    ctx.close()
+    say("  same evolution with another chunking")
+    ctx2 = lise.Context(w.lattice, w.M, w.functional)
+    ctx2.set_tuning(chunk_qpwf=3000, jgroup=8, no_overlap=1)
+    upload(ctx2, w)
+    ctx2.step(w.dt, 6)
+    psi2 = ctx2.get_qpwf(0, 64)
+    ctx2.close()
+    assert np.max(np.abs(psi - psi2)) < 1e-13 * np.max(np.abs(psi))
+
+
+def test_config2_full_size_fp32_density_error(lise):
+    w = wl.config2()
+    out = {}
+    for prec in (wl.FP64, wl.FP32):
+        w.functional.precision = prec
+        say(f"full size {w.name} precision {prec}: 10 steps")
+        ctx = lise.Context(w.lattice, w.M, w.functional)
+        upload(ctx, w)
+        ctx.step(w.dt, 10)
+        out[prec] = ctx.densities()
+        ctx.close()
+    en = np.linalg.norm(out[wl.FP32][0] - out[wl.FP64][0]) / np.linalg.norm(out[wl.FP64][0])
+    ek = np.linalg.norm(out[wl.FP32][1] - out[wl.FP64][1]) / np.linalg.norm(out[wl.FP64][1])
+    say(f"  FP32 vs FP64 density rel L2: n {en:.2e} kappa {ek:.2e}")
+    assert en < 1e-5 and ek < 1e-5

@@ -328,6 +328,9 @@ def batch_systems():
     return out
 
 
+@pytest.mark.skip(reason="capturing all systems of a batch into one graph crashed the host process "
+                         "(SIGSEGV inside lise_batch_step); that capture is removed and its cause was not shown. "
+                         "test_batch_per_system_streams_bitwise covers the batch path that replaced it")
 def test_batch_matches_individual_systems_bitwise(lise):
     """A batch of uneven systems (lattices 8^3..20^3, C = 2 and 4, FP64 and FP32) stepped
     through one graph equals each system stepped alone."""
@@ -358,6 +361,42 @@ def test_batch_matches_individual_systems_bitwise(lise):
     ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
     ev.step(dt, 10)
     assert rel_l2(got[1], ev.y) < 1e-11
+
+
+def test_batch_per_system_streams_bitwise(lise):
+    """A batch of uneven systems (lattices 8^3..20^3, C = 2 and 4, FP64 and FP32), each on
+    its own forked stream with its own four-step graph replays, equals each system stepped
+    alone; a second call continues from the first."""
+    systems = batch_systems()
+    dt = 0.002
+    say("batch of 4 systems on forked streams, 10 + 5 steps")
+    ctxs = []
+    for w in systems:
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_qpwf(0, w.qpwfs())
+        ctxs.append(c)
+    b = lise.Batch(ctxs)
+    b.step(dt, 10)
+    b.step(dt, 5)
+    got = [(c.get_qpwf(0, w.M), c.time()) for c, w in zip(ctxs, systems)]
+    b.close()
+    for c in ctxs:
+        c.close()
+    for w, (g, t) in zip(systems, got):
+        say(f"  alone: {w.name}")
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_qpwf(0, w.qpwfs())
+        c.step(dt, 10)
+        c.step(dt, 5)
+        ref = c.get_qpwf(0, w.M)
+        tref = c.time()
+        c.close()
+        assert t == tref, w.name
+        assert np.array_equal(g, ref), w.name
+    w = systems[1]
+    ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
+    ev.step(dt, 15)
+    assert rel_l2(got[1][0], ev.y) < 1e-11
 
 
 def test_autotune_runs_and_keeps_invariants(lise):
