@@ -82,6 +82,11 @@ typedef enum {
  * C = 4 densities (Eq. rho_t, nu_t, singlet average):
  *   n = sum_j (|v_up|^2 + |v_dn|^2), kappa = 1/2 sum_j (v_dn^* u_up - v_up^* u_dn).
  * frozen = 1 replaces U and Delta by the constants U0 and Delta0 (test mode).
+ * regularize = 1 replaces g by the lattice-renormalised coupling of
+ * Eq. (geff_3D) for a cubic lattice with its natural cutoff (m* = m = 1):
+ *   1/g_eff = 1/g - K / (4 pi a),
+ *   K = (12/pi) int_0^{pi/4} ln(1 + 1/cos^2 t) dt = 2.44274960780633...
+ * in Delta and in E_pair; regularize = 0 keeps the bare g.
  * C = 2 uses mu_up as its single chemical potential. */
 typedef struct {
     int32_t ncomp;          /* 2 or 4 */
@@ -89,7 +94,7 @@ typedef struct {
     double mu_up, mu_dn;
     double beta, g, w;
     int32_t frozen;
-    int32_t reserved;
+    int32_t regularize;     /* 0 or 1, see above */
     double U0, Delta0_re, Delta0_im;
     double ext_A, ext_w;
     double ext_r0[3];
@@ -217,6 +222,12 @@ int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *tot
  * written to *chosen (may be NULL).  Runs the start-up first if needed.
  * Errors: ARG, STATE, HIP, NAN. */
 int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);
+
+/* The coupling g that Delta = -g kappa uses for this lattice and functional
+ * (g itself, or g_eff when fn->regularize = 1), written to *g_out.  Host-only
+ * arithmetic: needs no device and no context.
+ * Errors: ARG (null pointer, regularize not 0/1, g = 0 or divergent g_eff). */
+int lise_coupling(const lise_lattice *lat, const lise_functional *fn, double *g_out);
 
 /* Batch of independent systems (for example different lattices and qpwf
  * counts) advanced together.  lise_batch_create takes nsys distinct contexts

@@ -1,7 +1,7 @@
 """CPU FP64 oracle of the TDSLDA time step (TEST INFRASTRUCTURE ONLY).
 
 This module is the slow, plain reference that the GPU library is checked
-against.  Only the test suite, the smoke check of the graft entry point and
+against.  Only the test suite, the smoke check of the entry module and
 the CPU-baseline leg of the benchmark may import it; the product path never
 calls it.  It shares no code with the HIP library: it has its own lattice,
 its own dense DFT matrices (no FFT library), its own Hamiltonian, densities,
@@ -138,10 +138,36 @@ def external_potential(lat, fn, t):
     return fn.ext_A * ramp * np.exp(-d2 / (2.0 * fn.ext_w ** 2))
 
 
+def lattice_K():
+    """K = (12 / pi) * int_0^{pi/4} ln(1 + 1 / cos^2 theta) d theta (Eq. geff_3D),
+    by adaptive quadrature of the printed integral."""
+    from scipy.integrate import quad
+    val, _ = quad(lambda th: math.log1p(1.0 / math.cos(th) ** 2), 0.0, math.pi / 4.0,
+                  epsabs=1e-14, epsrel=1e-13, limit=200)
+    return 12.0 / math.pi * val
+
+
+def effective_coupling(fn, lat):
+    """Coupling used in Delta = -g kappa and E_pair.
+
+    fn.regularize = 0: the bare g.  fn.regularize = 1: the lattice
+    renormalisation of Eq. (geff_3D) for a cubic lattice with its natural
+    cutoff, 1/g_eff = 1/g - (m* / (4 pi^2 hbar^2)) (pi / a) K, here with
+    m* = m = hbar = 1, i.e. 1/g_eff = 1/g - K / (4 pi a).
+    """
+    if not getattr(fn, "regularize", 0):
+        return fn.g
+    inv = 1.0 / fn.g - lattice_K() / (4.0 * math.pi * lat.a)
+    if inv == 0.0:
+        raise ValueError("regularised coupling diverges (1/g = K / (4 pi a))")
+    return 1.0 / inv
+
+
 def potentials(n, kappa, lat, fn, t):
     """V = U + U_ext and Delta.
 
-    Self-consistent: U = beta n^{2/3}, Delta = -g kappa (Eq. pairingfield).
+    Self-consistent: U = beta n^{2/3}, Delta = -g kappa (Eq. pairingfield),
+    g replaced by g_eff of Eq. (geff_3D) when fn.regularize is set.
     Frozen (test mode): U = U0 and Delta = Delta0 everywhere.
     """
     if fn.frozen:
@@ -149,7 +175,7 @@ def potentials(n, kappa, lat, fn, t):
         Delta = np.full(n.shape, complex(fn.Delta0))
     else:
         U = fn.beta * np.cbrt(n) ** 2
-        Delta = -fn.g * kappa
+        Delta = -effective_coupling(fn, lat) * kappa
     return U + external_potential(lat, fn, t), Delta
 
 
@@ -313,7 +339,7 @@ def observables(psi, lat, fn, t):
     E = E_kin + E_int + E_pair + E_ext with
       E_kin  = a^3 sum_r [weight * sum_k v_k^* (T v_k)]   (same T as the step),
       E_int  = a^3 sum_r (3/5) beta n^{5/3}   (so that dE/dn = U),
-      E_pair = a^3 sum_r g |kappa|^2          (Eq. pairing),
+      E_pair = a^3 sum_r g |kappa|^2          (Eq. pairing; g_eff when regularised),
       E_ext  = a^3 sum_r U_ext n.
     <|Delta|> = int |Delta| n / int n; r_cm = int r n / int n.
     """
@@ -330,7 +356,7 @@ def observables(psi, lat, fn, t):
         ekin += wt * a3 * float(np.sum(np.real(np.conj(psi[:, c]) * kinetic(psi[:, c], lat))))
     N = a3 * float(np.sum(n))
     e_int = a3 * float(np.sum(0.6 * fn.beta * np.cbrt(n) ** 5))
-    e_pair = a3 * float(np.sum(fn.g * np.abs(kappa) ** 2))
+    e_pair = a3 * float(np.sum(effective_coupling(fn, lat) * np.abs(kappa) ** 2))
     e_ext = a3 * float(np.sum(Uext * n))
     xs = [np.arange(m) * lat.a for m in (lat.nx, lat.ny, lat.nz)]
     tot = float(np.sum(n))

@@ -95,6 +95,7 @@ struct lise_ctx {
     std::vector<char> set_mask;   // which qpwfs were set (coarse: count)
     long long n_set = 0;
     bool dens_valid = false;
+    double g_used = 0.0;       // coupling of Delta = -g kappa (bare or regularised)
     bool hist = false;
     bool norms0_valid = false;
     double dt_hist = 0.0;
@@ -316,7 +317,7 @@ FieldParams field_params(const lise_ctx* c) {
     f.nz = c->lat.nz;
     f.a = c->lat.a;
     f.beta = c->fn.beta;
-    f.g = c->fn.g;
+    f.g = c->g_used;
     f.frozen = c->fn.frozen;
     f.U0 = c->fn.U0;
     f.D0re = c->fn.Delta0_re;
@@ -975,6 +976,9 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
                          lat->nx, lat->ny, lat->nz));
     if (n_qpwf < 1) return bail(fail(c, LISE_E_ARG, "n_qpwf must be >= 1"));
     if (fn->ncomp != 2 && fn->ncomp != 4) return bail(fail(c, LISE_E_ARG, "ncomp must be 2 or 4"));
+    if (fn->regularize != 0 && fn->regularize != 1) return bail(fail(c, LISE_E_ARG, "regularize must be 0 or 1"));
+    if (!lise::plan::effective_coupling(fn->g, lat->a, fn->regularize, &c->g_used))
+        return bail(fail(c, LISE_E_ARG, "regularised coupling undefined (g = 0 or 1/g = K / (4 pi a))"));
     if (fn->precision != LISE_FP64 && fn->precision != LISE_FP32 && fn->precision != LISE_FP32_MFMA)
         return bail(fail(c, LISE_E_UNSUPPORTED, "precision %d not supported", fn->precision));
     if (fn->precision == LISE_FP32_MFMA && !(lat->nx == lat->ny && mfma_side(lat->nx)))
@@ -1415,6 +1419,12 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
 const char* lise_last_error(const lise_ctx* c) { return c ? c->err : "null context"; }
 
 const char* lise_version(void) { return kVersion; }
+
+int lise_coupling(const lise_lattice* lat, const lise_functional* fn, double* g_out) {
+    if (!lat || !fn || !g_out) return LISE_E_ARG;
+    if (fn->regularize != 0 && fn->regularize != 1) return LISE_E_ARG;
+    return lise::plan::effective_coupling(fn->g, lat->a, fn->regularize, g_out) ? LISE_OK : LISE_E_ARG;
+}
 
 void lise_free(lise_ctx* c) {
     if (!c) return;

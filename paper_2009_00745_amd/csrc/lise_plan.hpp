@@ -128,6 +128,37 @@ inline std::vector<unsigned short> kinetic_matrix_bf16(int n, double a) {
     return out;
 }
 
+// K of the cubic-lattice coupling renormalisation (Eq. geff_3D):
+// (12/pi) * integral over [0, pi/4] of ln(1 + 1/cos^2 t) dt, composite Simpson
+// rule on 4096 panels in long double (smooth integrand: error far below 1e-16).
+inline long double lattice_K() {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const int n = 4096;
+    const long double h = (pi / 4.0L) / n;
+    auto f = [](long double t) {
+        const long double c = cosl(t);
+        return log1pl(1.0L / (c * c));
+    };
+    long double s = f(0.0L) + f(pi / 4.0L);
+    for (int i = 1; i < n; ++i) s += (i & 1 ? 4.0L : 2.0L) * f(i * h);
+    return 12.0L / pi * (s * h / 3.0L);
+}
+
+// Coupling g used in Delta = -g kappa: the bare g, or with regularisation the
+// g_eff of 1/g_eff = 1/g - m* K / (4 pi^2 hbar^2) * (pi / a) with m* = hbar = 1.
+// Returns false when 1/g_eff is zero (divergent coupling) or g is zero.
+inline bool effective_coupling(double g, double a, int regularize, double* out) {
+    if (!regularize) {
+        *out = g;
+        return true;
+    }
+    if (g == 0.0 || !(a > 0.0)) return false;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double inv = 1.0L / g - lattice_K() / (4.0L * pi * a);
+    if (inv == 0.0L) return false;
+    *out = (double)(1.0L / inv);
+    return true;
+}
 
 }  // namespace plan
 }  // namespace lise

@@ -21,7 +21,7 @@ ERRORS = {0: "OK", -1: "LISE_E_ARG", -2: "LISE_E_NOMEM", -3: "LISE_E_UNSUPPORTED
 SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_startup",
            "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
-           "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune",
+           "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune", "lise_coupling",
            "lise_batch_create", "lise_batch_step", "lise_batch_last_error", "lise_batch_free"]
 
 
@@ -34,7 +34,7 @@ class Functional(ct.Structure):
     _fields_ = [("ncomp", ct.c_int32), ("precision", ct.c_int32),
                 ("mu_up", ct.c_double), ("mu_dn", ct.c_double),
                 ("beta", ct.c_double), ("g", ct.c_double), ("w", ct.c_double),
-                ("frozen", ct.c_int32), ("reserved", ct.c_int32),
+                ("frozen", ct.c_int32), ("regularize", ct.c_int32),
                 ("U0", ct.c_double), ("Delta0_re", ct.c_double), ("Delta0_im", ct.c_double),
                 ("ext_A", ct.c_double), ("ext_w", ct.c_double),
                 ("ext_r0", ct.c_double * 3), ("ext_t_on", ct.c_double)]
@@ -92,6 +92,7 @@ def load_library(path=LIB_PATH):
         "lise_version": ([], ct.c_char_p),
         "lise_free": ([P], None),
         "lise_autotune": ([P, ct.c_double, ct.c_int32, ct.POINTER(Tuning)], ct.c_int),
+        "lise_coupling": ([ct.POINTER(Lattice), ct.POINTER(Functional), ct.POINTER(ct.c_double)], ct.c_int),
         "lise_batch_create": ([ct.POINTER(P), ct.c_int32, ct.POINTER(P), P], ct.c_int),
         "lise_batch_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
         "lise_batch_last_error": ([P], ct.c_char_p),
@@ -107,6 +108,26 @@ def load_library(path=LIB_PATH):
 
 class LiseError(RuntimeError):
     pass
+
+
+def functional_struct(f):
+    """lise_functional from an object with the fields of workloads.Functional."""
+    d0 = complex(f.Delta0)
+    return Functional(f.ncomp, f.precision, f.mu_up, f.mu_dn, f.beta, f.g, f.w,
+                      int(f.frozen), int(getattr(f, "regularize", 0)), f.U0, d0.real, d0.imag,
+                      f.ext_A, f.ext_w, (ct.c_double * 3)(*f.ext_r0), f.ext_t_on)
+
+
+def coupling(lattice, functional):
+    """The coupling g of Delta = -g kappa that the library uses (host-only call)."""
+    lib = load_library()
+    lat = Lattice(lattice.nx, lattice.ny, lattice.nz, 0, lattice.a)
+    fn = functional_struct(functional)
+    g = ct.c_double()
+    rc = lib.lise_coupling(ct.byref(lat), ct.byref(fn), ct.byref(g))
+    if rc != 0:
+        raise LiseError(f"lise_coupling: {ERRORS.get(rc, rc)}")
+    return g.value
 
 
 def _ptr(x):
@@ -131,11 +152,7 @@ class Context:
         self.C = int(functional.ncomp)
         self.N = self.nx * self.ny * self.nz
         lat = Lattice(lattice.nx, lattice.ny, lattice.nz, 0, lattice.a)
-        f = functional
-        d0 = complex(f.Delta0)
-        fn = Functional(f.ncomp, f.precision, f.mu_up, f.mu_dn, f.beta, f.g, f.w,
-                        int(f.frozen), 0, f.U0, d0.real, d0.imag, f.ext_A, f.ext_w,
-                        (ct.c_double * 3)(*f.ext_r0), f.ext_t_on)
+        fn = functional_struct(functional)
         self._h = ct.c_void_p()
         rc = self.lib.lise_init(ct.byref(self._h), ct.byref(lat), self.M, ct.byref(fn),
                                 ct.c_void_p(stream or 0))

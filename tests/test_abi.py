@@ -53,3 +53,33 @@ def test_bad_arguments_rejected():
         lise.Context(_Lat(8), 4, wl.Functional(ncomp=3))
     with pytest.raises(lise.LiseError, match="ARG"):
         lise.Context(_Lat(8, a=-1.0), 4, wl.Functional(ncomp=2))
+
+
+@pytest.mark.parametrize("a,g,reg", [(1.0, 1.5, 0), (1.0, 1.5, 1), (0.5, 1.5, 1), (1.25, -2.0, 1)])
+def test_library_coupling_matches_oracle(a, g, reg):
+    """lise_coupling (host-only arithmetic) equals the oracle's g of Eq. (geff_3D)."""
+    import oracle
+    import workloads as wl
+    lat = wl.Lattice(8, 8, 8, a)
+    fn = wl.Functional(ncomp=2, g=g, regularize=reg)
+    ref = oracle.effective_coupling(fn, lat)
+    assert abs(lise.coupling(lat, fn) - ref) <= 4e-16 * abs(ref)
+
+
+def test_library_coupling_rejects_bad_input():
+    import math
+    import oracle
+    import workloads as wl
+    lat = wl.Lattice(8, 8, 8, 1.0)
+    with pytest.raises(lise.LiseError, match="ARG"):
+        lise.coupling(lat, wl.Functional(ncomp=2, g=1.5, regularize=2))
+    with pytest.raises(lise.LiseError, match="ARG"):
+        lise.coupling(lat, wl.Functional(ncomp=2, g=0.0, regularize=1))
+    # 1/g = K / (4 pi a) makes g_eff diverge; the library may land one ulp away, so
+    # only require that it either rejects or returns a huge coupling
+    g_div = 4 * math.pi / oracle.lattice_K()
+    try:
+        v = lise.coupling(lat, wl.Functional(ncomp=2, g=g_div, regularize=1))
+        assert abs(v) > 1e12
+    except lise.LiseError:
+        pass

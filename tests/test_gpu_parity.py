@@ -152,6 +152,21 @@ def test_config2_reduced_with_bump(lise):
     assert abs(obs["E"] - o["E"]) < 1e-10 * abs(o["E"])
 
 
+def test_regularised_coupling_step(lise):
+    """Eq. (geff_3D) coupling (regularize = 1) on the 16^3 config-2 recipe, M = 24, and
+    on a C = 4 8^3 set, 12 ABM steps each, against the oracle."""
+    for w in (wl.config2(M=24, n=16), wl.config4(M=24, n=8, precision=wl.FP64)):
+        w.functional.regularize = 1
+        say(f"step {w.name} regularised, 12 steps")
+        got, n, k, t, s, obs, ev = run_pair(lise, w, 12)
+        n0, k0 = oracle.densities(ev.y, w.functional)
+        e = (rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0))
+        say(f"  rel L2: {e}")
+        assert max(e) < 1e-11
+        o = oracle.observables(ev.y, w.lattice, w.functional, ev.t)
+        assert abs(obs["E_pair"] - o["E_pair"]) < 1e-10 * abs(o["E_pair"])
+
+
 def test_four_component_step(lise):
     """C = 4 spin-imbalanced set on 8^3 (FP64), 20 ABM steps."""
     w = wl.config4(M=48, n=8, precision=wl.FP64)

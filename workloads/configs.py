@@ -41,6 +41,7 @@ class Functional:
     g: float = 0.0
     w: float = 2.0
     frozen: int = 0
+    regularize: int = 0
     U0: float = 0.0
     Delta0: complex = 0j
     ext_A: float = 0.0
