@@ -223,6 +223,32 @@ int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *tot
  * Errors: ARG, STATE, HIP, NAN. */
 int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);
 
+/* Checkpoint and restart (Sec. "Checkpoint and restart").
+ * lise_save writes the current state to the file `path` (created or
+ * truncated).  with_history = 0 saves the latest qpwfs only, as the paper
+ * does: a context that loads such a file restarts with the series-expansion
+ * start-up at its next lise_step.  with_history = 1 (allowed once the ABM
+ * history exists, i.e. after lise_startup or lise_step) also saves y_{n-1},
+ * y'_{n-1}, y'_{n-2}, y'_{n-3}, p_n - c_n and the densities of y_n, so that
+ * load + lise_step continues bit for bit as if never interrupted.
+ * File layout, little-endian: a 112-byte header
+ *   char magic[8] = "LISECKP1"; int32 version = 1, ncomp, precision, nx, ny,
+ *   nz, history, elem_bytes (16 = complex128, 8 = complex64); float64 a;
+ *   int64 M; float64 t; int64 step; float64 dt (0 without history);
+ *   int64 reserved[4]
+ * then arrays of M*C*N complex numbers of elem_bytes each, in the element
+ * order of lise_set_qpwf: y_n; with history y_{n-1}, y'_{n-1}, y'_{n-2},
+ * y'_{n-3}, p_n - c_n and 3N float64 (n, Re kappa, Im kappa of y_n); last M
+ * float64 reference norms (the norms when the qpwfs were set).
+ * lise_load reads such a file into a context created with the same lattice,
+ * C, M and precision (else ARG) and restores t and the step count.  Both
+ * calls synchronise the context stream and stage through pinned host memory.
+ * Errors: ARG (path, file content, I/O), STATE (save before the qpwfs are
+ * set, or history requested without one), HIP, NOMEM.  A failed load leaves
+ * the context requiring lise_set_qpwf. */
+int lise_save(lise_ctx *c, const char *path, int32_t with_history);
+int lise_load(lise_ctx *c, const char *path);
+
 /* The coupling g that Delta = -g kappa uses for this lattice and functional
  * (g itself, or g_eff when fn->regularize = 1), written to *g_out.  Host-only
  * arithmetic: needs no device and no context.

@@ -321,6 +321,32 @@ class Evolver:
         self.t = t + dt
         self.step_count += 1
 
+    def checkpoint(self, with_history=True):
+        """Copy of what a restart needs (Sec. Checkpoint and restart).
+
+        The paper saves the latest qpwfs only and restarts with the series
+        expansion; with_history additionally keeps y_{n-1}, the three previous
+        derivatives and p_n - c_n, so that the ABM continues as if never
+        interrupted.
+        """
+        ck = dict(y=self.y.copy(), t=self.t, step=self.step_count)
+        if with_history and self.hist is not None:
+            h = self.hist
+            ck.update(y_nm1=h["y_nm1"].copy(), dprev=[d.copy() for d in h["dprev"]],
+                      d_n=h["d_n"].copy(), dt=self.dt)
+        return ck
+
+    @classmethod
+    def restore(cls, lat, fn, ck):
+        """Evolver continuing from a checkpoint (start-up first when it holds no history)."""
+        ev = cls(lat, fn, ck["y"], ck["t"])
+        ev.step_count = ck["step"]
+        if "d_n" in ck:
+            ev.hist = dict(y_n=ev.y, y_nm1=ck["y_nm1"].copy(), dprev=[d.copy() for d in ck["dprev"]],
+                           d_n=ck["d_n"].copy())
+            ev.dt = ck["dt"]
+        return ev
+
     def step(self, dt, nsteps):
         """Advance nsteps ABM steps; the start-up runs first when needed."""
         if self.hist is None or self.dt != dt:

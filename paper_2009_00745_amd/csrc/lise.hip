@@ -951,7 +951,87 @@ int bfail(lise_batch* b, int code, const char* fmt, ...) {
     return code;
 }
 
+// ---- checkpoint files ----------------------------------------------------------------
+// Layout (little-endian): CkptHeader, then arrays of M*C*N complex numbers in
+// the context's own precision: y_n; with history also y_{n-1}, y'_{n-1},
+// y'_{n-2}, y'_{n-3}, p_n - c_n and the densities (3N float64: n, Re kappa,
+// Im kappa) of y_n; last the reference norms (M float64).
+
+struct CkptHeader {
+    char magic[8];
+    int32_t version, ncomp, precision, nx, ny, nz, history, elem_bytes;
+    double a;
+    int64_t M;
+    double t;
+    int64_t step;
+    double dt;
+    int64_t reserved[4];
+};
+static_assert(sizeof(CkptHeader) == 112, "checkpoint header layout");
+constexpr char kCkptMagic[8] = {'L', 'I', 'S', 'E', 'C', 'K', 'P', '1'};
+
+// Pinned staging, two buffers so that one copy engine transfer overlaps the
+// file I/O of the other buffer.
+struct Staging {
+    void* h[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    size_t cap = 0;
+    ~Staging() {
+        for (int i = 0; i < 2; ++i) {
+            if (ev[i]) (void)hipEventSynchronize(ev[i]), (void)hipEventDestroy(ev[i]);
+            if (h[i]) (void)hipHostFree(h[i]);
+        }
+    }
+};
+
+int staging_init(lise_ctx* c, Staging* st, size_t cap) {
+    st->cap = cap;
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(c, hipHostMalloc(&st->h[i], cap, hipHostMallocDefault));
+        HIPCHK(c, hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming));
+    }
+    return LISE_OK;
+}
+
+// device -> file, in pieces of the staging size
+int write_device(lise_ctx* c, Staging* st, FILE* f, const void* dev, size_t bytes) {
+    const char* src = static_cast<const char*>(dev);
+    const size_t np = (bytes + st->cap - 1) / st->cap;
+    if (np == 0) return LISE_OK;
+    HIPCHK(c, hipMemcpyAsync(st->h[0], src, std::min(st->cap, bytes), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(st->ev[0], c->stream));
+    for (size_t i = 0; i < np; ++i) {
+        const int b = (int)(i & 1);
+        const size_t off = i * st->cap, len = std::min(st->cap, bytes - off);
+        if (i + 1 < np) {
+            const size_t o2 = off + st->cap, l2 = std::min(st->cap, bytes - o2);
+            HIPCHK(c, hipMemcpyAsync(st->h[1 - b], src + o2, l2, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipEventRecord(st->ev[1 - b], c->stream));
+        }
+        HIPCHK(c, hipEventSynchronize(st->ev[b]));
+        if (fwrite(st->h[b], 1, len, f) != len) return fail(c, LISE_E_ARG, "checkpoint write failed");
+        // the next copy into this buffer is issued only after the write above
+    }
+    return LISE_OK;
+}
+
+// file -> device, in pieces of the staging size
+int read_device(lise_ctx* c, Staging* st, FILE* f, void* dev, size_t bytes) {
+    char* dst = static_cast<char*>(dev);
+    for (size_t off = 0, i = 0; off < bytes; off += st->cap, ++i) {
+        const int b = (int)(i & 1);
+        const size_t len = std::min(st->cap, bytes - off);
+        HIPCHK(c, hipEventSynchronize(st->ev[b]));   // the previous copy out of this buffer is done
+        if (fread(st->h[b], 1, len, f) != len) return fail(c, LISE_E_ARG, "checkpoint file truncated");
+        HIPCHK(c, hipMemcpyAsync(dst + off, st->h[b], len, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipEventRecord(st->ev[b], c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LISE_OK;
+}
+
 }  // namespace
+
 
 // =============================================================================
 // C-ABI
@@ -1267,6 +1347,106 @@ int lise_memory(const lise_ctx* c, int64_t* bytes) {
     b += (long long)c->slot_cap * 3 * c->N * 8;
     b += 10LL * c->N * 8;
     *bytes = b;
+    return LISE_OK;
+}
+
+int lise_save(lise_ctx* c, const char* path, int32_t with_history) {
+    if (!c || !path) return LISE_E_ARG;
+    if (with_history != 0 && with_history != 1) return fail(c, LISE_E_ARG, "with_history must be 0 or 1");
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set");
+    if (with_history && !c->hist) return fail(c, LISE_E_STATE, "no ABM history to save (step first)");
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.ncomp = c->C;
+    h.precision = c->fn.precision;
+    h.nx = c->lat.nx;
+    h.ny = c->lat.ny;
+    h.nz = c->lat.nz;
+    h.history = with_history;
+    h.elem_bytes = (int32_t)c->esz;
+    h.a = c->lat.a;
+    h.M = c->M;
+    h.t = c->t;
+    h.step = c->step;
+    h.dt = with_history ? c->dt_hist : 0.0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, LISE_E_ARG, "cannot open %s for writing", path);
+    Staging st;
+    int rc = staging_init(c, &st, 64u << 20);
+    if (rc == LISE_OK && fwrite(&h, sizeof(h), 1, f) != 1) rc = fail(c, LISE_E_ARG, "checkpoint write failed");
+    const size_t arr = (size_t)c->M * c->per * c->esz;
+    std::vector<int> bufs = {c->iy};
+    if (with_history) {
+        bufs.push_back(1 - c->iy);
+        for (int k = 3; k >= 1; --k) bufs.push_back(2 + (c->dn + k) % 4);   // y'_{n-1}, y'_{n-2}, y'_{n-3}
+        bufs.push_back(6);
+    }
+    for (int b : bufs)
+        if (rc == LISE_OK) rc = write_device(c, &st, f, c->buf[b], arr);
+    if (rc == LISE_OK && with_history) rc = write_device(c, &st, f, c->dens_cur, 3 * (size_t)c->N * sizeof(double));
+    if (rc == LISE_OK) rc = write_device(c, &st, f, c->norms0, (size_t)c->M * sizeof(double));
+    if (fclose(f) != 0 && rc == LISE_OK) rc = fail(c, LISE_E_ARG, "checkpoint close failed");
+    return rc;
+}
+
+int lise_load(lise_ctx* c, const char* path) {
+    if (!c || !path) return LISE_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(c, LISE_E_ARG, "cannot open %s", path);
+    CkptHeader h;
+    int rc = LISE_OK;
+    if (fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+        rc = fail(c, LISE_E_ARG, "%s is not a version-1 checkpoint", path);
+    else if (h.ncomp != c->C || h.precision != c->fn.precision || h.nx != c->lat.nx || h.ny != c->lat.ny ||
+             h.nz != c->lat.nz || h.a != c->lat.a || h.M != c->M || h.elem_bytes != (int32_t)c->esz ||
+             (h.history != 0 && h.history != 1))
+        rc = fail(c, LISE_E_ARG, "checkpoint does not match the context (lattice, C, M or precision)");
+    else if (!std::isfinite(h.t) || (h.history && !(std::isfinite(h.dt) && h.dt != 0.0)))
+        rc = fail(c, LISE_E_ARG, "checkpoint holds a non-finite time or step size");
+    Staging st;
+    if (rc == LISE_OK) rc = staging_init(c, &st, 64u << 20);
+    const size_t arr = (size_t)c->M * c->per * c->esz;
+    // canonical placement: y_n in buffer 0, y_{n-1} in 1, derivatives as after dn = 0
+    std::vector<int> bufs = {0};
+    if (h.history && rc == LISE_OK) {
+        bufs.push_back(1);
+        for (int k = 3; k >= 1; --k) bufs.push_back(2 + k % 4);
+        bufs.push_back(6);
+    }
+    for (int b : bufs)
+        if (rc == LISE_OK) rc = read_device(c, &st, f, c->buf[b], arr);
+    if (rc == LISE_OK && h.history) rc = read_device(c, &st, f, c->dens_cur, 3 * (size_t)c->N * sizeof(double));
+    if (rc == LISE_OK) rc = read_device(c, &st, f, c->norms0, (size_t)c->M * sizeof(double));
+    fclose(f);
+    if (rc != LISE_OK) {
+        // the state may be partly overwritten: require a fresh set
+        c->n_set = 0;
+        c->hist = false;
+        c->dens_valid = false;
+        return rc;
+    }
+    c->iy = 0;
+    c->dn = 0;
+    c->n_set = c->M;
+    c->norms0_valid = true;
+    c->t = h.t;
+    c->step = h.step;
+    c->config_version += 1;    // buffer roles changed: no stale graph replays
+    HIPCHK(c, hipMemcpyAsync(c->dtime, &c->t, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (h.history) {
+        c->hist = true;
+        c->dt_hist = h.dt;
+        c->dens_valid = true;
+        CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
+    } else {
+        c->hist = false;
+        c->dens_valid = false;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LISE_OK;
 }
 

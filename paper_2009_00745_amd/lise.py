@@ -22,6 +22,7 @@ SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_
            "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
            "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune", "lise_coupling",
+           "lise_save", "lise_load",
            "lise_batch_create", "lise_batch_step", "lise_batch_last_error", "lise_batch_free"]
 
 
@@ -92,6 +93,8 @@ def load_library(path=LIB_PATH):
         "lise_version": ([], ct.c_char_p),
         "lise_free": ([P], None),
         "lise_autotune": ([P, ct.c_double, ct.c_int32, ct.POINTER(Tuning)], ct.c_int),
+        "lise_save": ([P, ct.c_char_p, ct.c_int32], ct.c_int),
+        "lise_load": ([P, ct.c_char_p], ct.c_int),
         "lise_coupling": ([ct.POINTER(Lattice), ct.POINTER(Functional), ct.POINTER(ct.c_double)], ct.c_int),
         "lise_batch_create": ([ct.POINTER(P), ct.c_int32, ct.POINTER(P), P], ct.c_int),
         "lise_batch_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
@@ -242,6 +245,14 @@ class Context:
         t = Tuning()
         self._check(self.lib.lise_autotune(self._h, dt, trial_steps, ct.byref(t)), "lise_autotune")
         return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def save(self, path, with_history=True):
+        """Write a checkpoint file (with the ABM history: bit-exact continuation)."""
+        self._check(self.lib.lise_save(self._h, os.fsencode(path), int(bool(with_history))), "lise_save")
+
+    def load(self, path):
+        """Read a checkpoint written by save() for the same lattice, C, M and precision."""
+        self._check(self.lib.lise_load(self._h, os.fsencode(path)), "lise_load")
 
     def memory(self):
         b = ct.c_int64()

@@ -333,6 +333,113 @@ def test_graph_replay_matches_eager_bitwise(lise):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def read_checkpoint(path):
+    """Reader of the checkpoint layout documented with lise_save."""
+    import struct
+    with open(path, "rb") as f:
+        hdr = f.read(112)
+        assert hdr[:8] == b"LISECKP1"
+        version, ncomp, prec, nx, ny, nz, hist, eb = struct.unpack("<8i", hdr[8:40])
+        a, M, t, step, dt = struct.unpack("<dqdqd", hdr[40:80])
+        dtype = np.complex128 if eb == 16 else np.complex64
+        shp = (M, ncomp, nz, ny, nx)
+        cnt = int(np.prod(shp))
+        arrays = [np.fromfile(f, dtype=dtype, count=cnt).reshape(shp) for _ in range(6 if hist else 1)]
+        dens = np.fromfile(f, dtype=np.float64, count=3 * nx * ny * nz) if hist else None
+        norms = np.fromfile(f, dtype=np.float64, count=M)
+        assert f.read() == b""
+    return dict(version=version, ncomp=ncomp, precision=prec, shape=shp, history=hist, a=a, t=t,
+                step=step, dt=dt, arrays=arrays, dens=dens, norms=norms)
+
+
+def test_checkpoint_with_history_continues_bitwise(lise, tmp_path):
+    """save(with_history) + load + step equals uninterrupted stepping bit for bit (FP64 with
+    overlap and graph replays, FP32), and the saved ABM history matches the oracle's."""
+    cases = [(wl.config2(M=24, n=16), {"graph": 1}), (wl.config3(M=16, n=20, precision=wl.FP32), {})]
+    for w, tuning in cases:
+        path = str(tmp_path / f"{w.name}.ckpt")
+        say(f"checkpoint {w.name}: 7 steps, save, 9 more; reload and 9 steps")
+        a = lise.Context(w.lattice, w.M, w.functional)
+        a.set_tuning(**tuning)
+        a.set_qpwf(0, w.qpwfs())
+        a.step(w.dt, 7)
+        a.save(path, with_history=True)
+        a.step(w.dt, 9)
+        ya, ta = a.get_qpwf(0, w.M), a.time()
+        na, ka = a.densities()
+        a.close()
+        b = lise.Context(w.lattice, w.M, w.functional)
+        b.set_tuning(**tuning)
+        b.load(path)
+        b.step(w.dt, 9)
+        yb, tb = b.get_qpwf(0, w.M), b.time()
+        nb, kb = b.densities()
+        b.close()
+        assert ta == tb
+        assert np.array_equal(ya, yb) and np.array_equal(na, nb) and np.array_equal(ka, kb)
+        if w.functional.precision == wl.FP64:
+            ck = read_checkpoint(path)
+            ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
+            ev.step(w.dt, 7)
+            ref = ev.checkpoint()
+            assert ck["history"] == 1 and ck["step"] == ev.step_count and abs(ck["t"] - ev.t) < 1e-14
+            assert ck["dt"] == w.dt
+            pairs = [(ck["arrays"][0], ref["y"]), (ck["arrays"][1], ref["y_nm1"]),
+                     (ck["arrays"][2], ref["dprev"][0]), (ck["arrays"][3], ref["dprev"][1]),
+                     (ck["arrays"][4], ref["dprev"][2])]
+            errs = [rel_l2(g, r) for g, r in pairs]
+            # p_n - c_n is O(dt^6 y^(6)): compare on the scale of y'
+            errs.append(float(np.linalg.norm(ck["arrays"][5] - ref["d_n"]) / np.linalg.norm(ref["dprev"][0])))
+            n0, k0 = oracle.densities(ref["y"], w.functional)
+            N = w.lattice.n
+            errs += [rel_l2(ck["dens"][:N], n0.ravel()),
+                     rel_l2(ck["dens"][N:2 * N] + 1j * ck["dens"][2 * N:], k0.ravel())]
+            say(f"  saved history vs oracle: {errs}")
+            assert max(errs) < 1e-11
+
+
+def test_checkpoint_qpwfs_only_restarts_like_the_oracle(lise, tmp_path):
+    """The paper's restart: latest qpwfs only, series start-up again after load."""
+    w = wl.config2(M=16, n=16)
+    path = str(tmp_path / "latest.ckpt")
+    say("checkpoint without history: 5 steps, save, load, start-up + 6 steps")
+    a = lise.Context(w.lattice, w.M, w.functional)
+    a.set_qpwf(0, w.qpwfs())
+    a.step(w.dt, 5)
+    a.save(path, with_history=False)
+    a.close()
+    b = lise.Context(w.lattice, w.M, w.functional)
+    b.load(path)
+    b.step(w.dt, 6)
+    got, (t, s) = b.get_qpwf(0, w.M), b.time()
+    b.close()
+    ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
+    ev.step(w.dt, 5)
+    r = oracle.Evolver.restore(w.lattice, w.functional, ev.checkpoint(with_history=False))
+    r.step(w.dt, 6)
+    assert s == r.step_count and abs(t - r.t) < 1e-13
+    assert rel_l2(got, r.y) < 1e-11
+    ck = read_checkpoint(path)
+    assert ck["history"] == 0 and ck["dens"] is None and len(ck["arrays"]) == 1
+
+
+def test_checkpoint_errors(lise, tmp_path):
+    w = wl.config1(M=16)
+    path = str(tmp_path / "e.ckpt")
+    c = lise.Context(w.lattice, w.M, w.functional)
+    c.set_qpwf(0, w.qpwfs())
+    with pytest.raises(lise.LiseError, match="STATE"):
+        c.save(path, with_history=True)          # no history yet
+    c.save(path, with_history=False)
+    c.close()
+    other = lise.Context(w.lattice, w.M + 1, w.functional)
+    with pytest.raises(lise.LiseError, match="ARG"):
+        other.load(path)                          # M differs
+    with pytest.raises(lise.LiseError, match="ARG"):
+        other.load(str(tmp_path / "missing.ckpt"))
+    other.close()
+
+
 def batch_systems():
     specs = [(wl.config1(M=64), wl.FP64), (wl.config2(M=24, n=16), wl.FP64),
              (wl.config3(M=16, n=20, precision=wl.FP32), wl.FP32), (wl.config4(M=12, n=8, precision=wl.FP64), wl.FP64)]
