@@ -87,6 +87,14 @@ typedef enum {
  *   1/g_eff = 1/g - K / (4 pi a),
  *   K = (12/pi) int_0^{pi/4} ln(1 + 1/cos^2 t) dt = 2.44274960780633...
  * in Delta and in E_pair; regularize = 0 keeps the bare g.
+ * remove_phase = 1 evolves every qpwf with H - eta_j instead of H
+ * (Eq. sp_en), eta_j = <psi_j|H|psi_j> = a^3 sum_r sum_c psi_c^* (H psi)_c
+ * of the vector H acts on, taken in every right-hand side: y'_n and m' of
+ * the ABM step, and in each series-expansion start-up step
+ * exp(-i dt (H_s - eta)) with eta from psi_s and the H of that
+ * propagation.  It removes the trivial phase of Eq. (phase) and leaves the
+ * densities unchanged up to the integration error.  Costs one more plane
+ * pass (reads psi and the z-term) per H application. 
  * C = 2 uses mu_up as its single chemical potential. */
 typedef struct {
     int32_t ncomp;          /* 2 or 4 */
@@ -99,6 +107,8 @@ typedef struct {
     double ext_A, ext_w;
     double ext_r0[3];
     double ext_t_on;
+    int32_t remove_phase;   /* 0 or 1, see above */
+    int32_t reserved;       /* must be 0 */
 } lise_functional;
 
 /* Observables of the current state (Sec. "Miscellaneous quantities" and the

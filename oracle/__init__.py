@@ -7,5 +7,5 @@ from .lise_oracle import (wavenumbers, dft_matrix, dft3, k_squared, kinetic,
                           densities, external_potential, potentials, apply_h,
                           hamiltonian_of, rhs, taylor_propagate, series_step,
                           abm_update, Evolver, observables, gram, lattice_K,
-                          effective_coupling,
+                          effective_coupling, quasiparticle_energies, apply_h_shifted,
                           ABM_P, ABM_C, ABM_M, ABM_Y)

@@ -23,7 +23,10 @@ Readings of passages that are silent, ambiguous or garbled:
     printed error constant 161/480).
   * Start-up: three series-expansion steps (order 4) fill y'_0..y'_2, y_2,
     y_3; the first modifier uses p_3 - c_3 = 0.
-  * Trivial-phase removal (Eq. sp_en) and per-step renormalisation are off.
+  * Trivial-phase removal (Eq. sp_en) is optional (fn.remove_phase): every
+    right-hand side takes eta_k of the vector it acts on; each series
+    propagation takes eta from its starting psi and its own H.  Per-step
+    renormalisation is not done (the paper finds it unnecessary).
   * C = 2 keeps the (u_up, v_dn) block of Eq. (tdslda) with h_updn = 0; its
     densities carry a weight w: n = w sum |v|^2, kappa = (w/2) sum v* u.
   * C = 4 uses the singlet average kappa = 1/2 sum (v_dn* u_up - v_up* u_dn),
@@ -210,6 +213,23 @@ def apply_h(psi, V, Delta, lat, fn):
     return out
 
 
+def quasiparticle_energies(psi, V, Delta, lat, fn):
+    """eta_k = <psi_k | H | psi_k> = a^3 sum_r sum_c psi_c^* (H psi)_c (Eq. sp_en).
+
+    H is Hermitian, so eta_k is real; the real part of the sum is taken.
+    """
+    Hpsi = apply_h(psi, V, Delta, lat, fn)
+    return lat.a ** 3 * np.real(np.sum(np.conj(psi) * Hpsi, axis=(1, 2, 3, 4)))
+
+
+def apply_h_shifted(psi, V, Delta, lat, fn, eta):
+    """(H - eta_k) psi_k for every qpwf k; eta None means plain H."""
+    Hpsi = apply_h(psi, V, Delta, lat, fn)
+    if eta is None:
+        return Hpsi
+    return Hpsi - eta[:, None, None, None, None] * psi
+
+
 def hamiltonian_of(psi, lat, fn, t):
     """Local fields of the Hamiltonian built from the densities of psi at time t."""
     n, kappa = densities(psi, fn)
@@ -217,20 +237,25 @@ def hamiltonian_of(psi, lat, fn, t):
 
 
 def rhs(psi, lat, fn, t):
-    """Right-hand side f(psi, t) = -i H[n(psi), kappa(psi), t] psi (Eq. tdslda, hbar = 1)."""
+    """Right-hand side f(psi, t) = -i H[n(psi), kappa(psi), t] psi (Eq. tdslda, hbar = 1).
+
+    With fn.remove_phase the trivial phase is removed (Eq. sp_en):
+    f = -i (H - eta_k) psi_k with eta_k = <psi_k | H | psi_k> of this psi.
+    """
     V, Delta = hamiltonian_of(psi, lat, fn, t)
-    return -1j * apply_h(psi, V, Delta, lat, fn)
+    eta = quasiparticle_energies(psi, V, Delta, lat, fn) if getattr(fn, "remove_phase", 0) else None
+    return -1j * apply_h_shifted(psi, V, Delta, lat, fn, eta)
 
 
 # ---------------------------------------------------------------------------
 # Series-expansion predictor-corrector (Sec. TDSLDA, "Time evolution")
 
-def taylor_propagate(psi, V, Delta, lat, fn, dt, order=4):
-    """sum_{q=0}^{order} (-i dt H)^q / q! psi with H fixed."""
+def taylor_propagate(psi, V, Delta, lat, fn, dt, order=4, eta=None):
+    """sum_{q=0}^{order} (-i dt (H - eta))^q / q! psi with H (and eta) fixed."""
     acc = psi.copy()
     term = psi
     for q in range(1, order + 1):
-        term = (-1j * dt / q) * apply_h(term, V, Delta, lat, fn)
+        term = (-1j * dt / q) * apply_h_shifted(term, V, Delta, lat, fn, eta)
         acc = acc + term
     return acc
 
@@ -241,14 +266,19 @@ def series_step(psi, lat, fn, t, dt, order=4):
     1. H(t) from the densities of psi(t); predictor psi_pre = exp(-i H dt) psi.
     2. Corrector densities (n_pre + n(t)) / 2 give H_cor, taken at t + dt/2.
     3. psi(t + dt) = exp(-i H_cor dt) psi(t).
-    The exponential is the order-4 series.
+    The exponential is the order-4 series.  With phase removal (Eq. sp_en)
+    each propagation uses H - eta with eta = <psi(t)|H|psi(t)> of the H of
+    that propagation (H(t) for the predictor, H_cor for the corrector).
     """
+    rp = getattr(fn, "remove_phase", 0)
     n0, k0 = densities(psi, fn)
     V, Delta = potentials(n0, k0, lat, fn, t)
-    pre = taylor_propagate(psi, V, Delta, lat, fn, dt, order)
+    eta = quasiparticle_energies(psi, V, Delta, lat, fn) if rp else None
+    pre = taylor_propagate(psi, V, Delta, lat, fn, dt, order, eta)
     n1, k1 = densities(pre, fn)
     Vc, Dc = potentials(0.5 * (n1 + n0), 0.5 * (k1 + k0), lat, fn, t + 0.5 * dt)
-    return taylor_propagate(psi, Vc, Dc, lat, fn, dt, order)
+    eta_c = quasiparticle_energies(psi, Vc, Dc, lat, fn) if rp else None
+    return taylor_propagate(psi, Vc, Dc, lat, fn, dt, order, eta_c)
 
 
 # ---------------------------------------------------------------------------

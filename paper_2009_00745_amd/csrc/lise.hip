@@ -96,6 +96,10 @@ struct lise_ctx {
     long long n_set = 0;
     bool dens_valid = false;
     double g_used = 0.0;       // coupling of Delta = -g kappa (bare or regularised)
+    int remove_phase = 0;      // Eq. (sp_en): evolve with H - eta_j
+    double* eta = nullptr;     // [M] eta_j of the vector the current H application acts on
+    double* eta_part = nullptr;  // [chunk][plane blocks] partial sums of the eta pass
+    long long eta_part_cap = 0;
     bool hist = false;
     bool norms0_valid = false;
     double dt_hist = 0.0;
@@ -205,6 +209,7 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 template <typename T>
@@ -218,7 +223,8 @@ void set_type_attrs(int lim) {
     set_fast_attrs<T, 64>(lim);
     const void* g[] = {(const void*)kp_kernel<T, 0, 4>, (const void*)kp_kernel<T, 1, 4>, (const void*)kp_kernel<T, 2, 4>,
                        (const void*)kp_kernel<T, 3, 4>, (const void*)kp_kernel<T, 0, 16>, (const void*)kp_kernel<T, 1, 16>,
-                       (const void*)kp_kernel<T, 2, 16>, (const void*)kp_kernel<T, 3, 16>, (const void*)kz_kernel<T>};
+                       (const void*)kp_kernel<T, 2, 16>, (const void*)kp_kernel<T, 3, 16>, (const void*)kp_kernel<T, 4, 4>,
+                       (const void*)kp_kernel<T, 4, 16>, (const void*)kz_kernel<T>};
     for (const void* f : g) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
@@ -228,6 +234,7 @@ void set_mfma_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_mfma<NS, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 void set_all_attrs(int lim) {
@@ -306,6 +313,15 @@ int configure(lise_ctx* c) {
         dfree(reinterpret_cast<void**>(&c->dpart));
         CHK(dalloc(c, reinterpret_cast<void**>(&c->dpart), (size_t)dens_slots * 3 * c->N * sizeof(double)));
         c->slot_cap = (int)dens_slots;
+    }
+    if (c->remove_phase) {
+        const long long need = c->chunk * (long long)(nz / c->zb);
+        if (c->eta_part_cap < need) {
+            dfree(reinterpret_cast<void**>(&c->eta_part));
+            CHK(dalloc(c, reinterpret_cast<void**>(&c->eta_part), (size_t)need * sizeof(double)));
+            c->eta_part_cap = need;
+        }
+        if (!c->eta) CHK(dalloc(c, reinterpret_cast<void**>(&c->eta), (size_t)c->M * sizeof(double)));
     }
     return LISE_OK;
 }
@@ -389,7 +405,7 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     a.kcount = k;
     if constexpr (std::is_same<T, float>::value) {
         if (c->mfma_xy) {
-            dim3 grid(c->lat.nz, (k + c->jg - 1) / c->jg);
+            dim3 grid(c->lat.nz, (k + a.jg - 1) / a.jg);
             hipEvent_t ev;
             prof_begin(c, cls, &ev);
             switch (c->lat.nx) {
@@ -403,7 +419,7 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
         }
     }
     if (c->fast_xy) {
-        dim3 grid(c->lat.nz, (k + c->jg - 1) / c->jg);
+        dim3 grid(c->lat.nz, (k + a.jg - 1) / a.jg);
         hipEvent_t ev;
         prof_begin(c, cls, &ev);
         switch (c->lat.nx) {
@@ -418,7 +434,7 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
         prof_end(c, cls, ev);
         return check_launch(c, "kp_fast");
     }
-    dim3 grid(c->lat.nz / c->zb, (k + c->jg - 1) / c->jg);
+    dim3 grid(c->lat.nz / c->zb, (k + a.jg - 1) / a.jg);
     // the kinetic-energy mode reuses LDS for a 256-double reduction
     const size_t lds = std::max(kp_lds_bytes(c, c->zb), (size_t)kThreads * sizeof(double));
     hipEvent_t ev;
@@ -490,8 +506,32 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
 // overlap on, the z-axis kernel of chunk c+1 runs on the internal stream
 // while the plane kernel of chunk c runs on the context stream; the two
 // z-scratch buffers alternate and events order every reuse.
+// eta_j = <x_j | H | x_j> (Eq. sp_en) for the qpwfs [j0, j0 + k) of the vector
+// x = main.in with the fields of `main`; needs the chunk's z-term in main.G.
+template <typename T>
+int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k) {
+    KPArgs<T> e = main;
+    e.jg = 1;
+    e.eta = nullptr;
+    e.dens_src = 0;
+    e.out = e.acc = e.deriv = nullptr;
+    e.a1 = e.a2 = e.a3 = e.a4 = e.a5 = e.a6 = nullptr;
+    e.epart = c->eta_part;
+    CHK((launch_kp_t<T, KP_ETA>(c, e, j0, k, 3)));
+    const int nblk = c->lat.nz / c->zb;
+    const double a3 = c->lat.a * c->lat.a * c->lat.a;
+    hipLaunchKernelGGL(eta_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, c->stream, c->eta_part,
+                       nblk, k, a3, c->eta + j0);
+    return check_launch(c, "eta_reduce_kernel");
+}
+
+// eta_op (phase removal of Eq. sp_en, ignored when it is off): 0 plain H;
+// 1 compute eta_j of a.in chunk by chunk and apply H - eta_j; 2 apply H - eta_j
+// with the eta_j computed by an earlier call.
 template <typename T, int MODE>
-int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int cls) {
+int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int cls, int eta_op = 0) {
+    if (!c->remove_phase) eta_op = 0;
+    a.eta = eta_op ? c->eta : nullptr;
     const int dens = a.dens_src;
     const bool ov = c->overlap && !c->fused && c->s2;
     if (ov) {
@@ -514,6 +554,7 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
         }
         a.G = reinterpret_cast<const cpx<T>*>(Gb);
         a.accumulate = (dens && ci > 0) ? 1 : 0;
+        if (eta_op == 1) CHK(eta_pass_t<T>(c, a, j0, k));
         CHK((launch_kp_t<T, MODE>(c, a, j0, k, cls)));
         if (ov) HIPCHK(c, hipEventRecord(c->ev_kp[b], c->stream));
     }
@@ -599,7 +640,7 @@ int taylor_t(lise_ctx* c, const cpx<T>* psi, cpx<T>* term, cpx<T>* acc, cpx<T>* 
         a.coef_re = 0.0;
         a.coef_im = -dt / q;
         a.dens_src = (q == 4);
-        CHK((apply_chunks<T, KP_APPLY>(c, a, 0, c->M, 3)));
+        CHK((apply_chunks<T, KP_APPLY>(c, a, 0, c->M, 3, q == 1 ? 1 : 2)));
     }
     return LISE_OK;
 }
@@ -658,7 +699,7 @@ int abm_step_t(lise_ctx* c) {
         a.a6 = S<T>(c, d0);
         a.dt = dt;
         a.dens_src = 1;
-        CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0)));
+        CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0, 1)));
     }
     CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, dt));
     // phase 2: H m -> m', y_{n+1}, p_{n+1} - c_{n+1}; densities of y_{n+1}
@@ -672,7 +713,7 @@ int abm_step_t(lise_ctx* c) {
         a.a5 = S<T>(c, 6);                          // p_n - c_n -> p_{n+1} - c_{n+1}
         a.dt = dt;
         a.dens_src = 1;
-        CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0)));
+        CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0, 1)));
     }
     CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, dt));
     CHK(tick(c, dt));
@@ -1057,6 +1098,9 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     if (n_qpwf < 1) return bail(fail(c, LISE_E_ARG, "n_qpwf must be >= 1"));
     if (fn->ncomp != 2 && fn->ncomp != 4) return bail(fail(c, LISE_E_ARG, "ncomp must be 2 or 4"));
     if (fn->regularize != 0 && fn->regularize != 1) return bail(fail(c, LISE_E_ARG, "regularize must be 0 or 1"));
+    if (fn->remove_phase != 0 && fn->remove_phase != 1) return bail(fail(c, LISE_E_ARG, "remove_phase must be 0 or 1"));
+    c->remove_phase = fn->remove_phase;
+    if (fn->reserved != 0) return bail(fail(c, LISE_E_ARG, "lise_functional.reserved must be 0"));
     if (!lise::plan::effective_coupling(fn->g, lat->a, fn->regularize, &c->g_used))
         return bail(fail(c, LISE_E_ARG, "regularised coupling undefined (g = 0 or 1/g = K / (4 pi a))"));
     if (fn->precision != LISE_FP64 && fn->precision != LISE_FP32 && fn->precision != LISE_FP32_MFMA)
@@ -1634,6 +1678,8 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->red));
     dfree(reinterpret_cast<void**>(&c->norms));
     dfree(reinterpret_cast<void**>(&c->norms0));
+    dfree(reinterpret_cast<void**>(&c->eta));
+    dfree(reinterpret_cast<void**>(&c->eta_part));
     dfree(reinterpret_cast<void**>(&c->bad));
     dfree(reinterpret_cast<void**>(&c->dtime));
     dfree(reinterpret_cast<void**>(&c->dkin));

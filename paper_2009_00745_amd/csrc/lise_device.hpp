@@ -229,7 +229,7 @@ __device__ __forceinline__ int signed_mode(int i, int n) { return (2 * i < n) ? 
 // ---------------------------------------------------------------------------
 // Kernel arguments
 
-enum KpMode { KP_APPLY = 0, KP_ABM1 = 1, KP_ABM2 = 2, KP_KINETIC = 3 };
+enum KpMode { KP_APPLY = 0, KP_ABM1 = 1, KP_ABM2 = 2, KP_KINETIC = 3, KP_ETA = 4 };
 
 template <typename T>
 struct KPArgs {
@@ -268,7 +268,10 @@ struct KPArgs {
     double* dpart;    // [slot][3][N] float64 density partial sums
     int dens_src;     // 0: none, 1: the produced vector (m, y_{n+1}, acc or out)
     int accumulate;   // 0: store partials, 1: add to them
-    double* epart;    // KP_KINETIC: one float64 per workgroup
+    double* epart;    // KP_KINETIC, KP_ETA: one float64 per workgroup
+    // per global qpwf: the instantaneous quasiparticle energy eta_j of
+    // Eq. (sp_en), subtracted from H in every mode that applies H (null: off)
+    const double* eta;
 };
 
 // ---------------------------------------------------------------------------
@@ -292,9 +295,14 @@ struct KPArgs {
 // y'_{n-3} and Y over y_{n-1} (d_n stays); phase 2 stores y_{n+1} over Y and
 // d_{n+1} over d_n.
 
+//
+// KP_ETA accumulates Re(f^* H f) of the pair (the summand of eta_j); with
+// phase removal on (a.eta set) the other modes apply H - eta_j (ej) instead
+// of H.
+
 template <typename T, int MODE>
 __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
-                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt,
+                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt, T ej,
                                                double& dn, double& dkr, double& dki, double& ekin) {
     if (MODE == KP_KINETIC) {
         ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
@@ -305,8 +313,17 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
     const cpx<T> Dl = mk(sg * T(a.D[2 * rpt]), sg * T(a.D[2 * rpt + 1]));
     const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
     // H u = (h - mu_a) u + s Delta v ;  H v = s Delta^* u - (h - mu_b) v
-    const cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
-    const cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
+    cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
+    cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
+    if (MODE == KP_ETA) {
+        ekin += double(fa.re) * double(Ha.re) + double(fa.im) * double(Ha.im) + double(fb.re) * double(Hb.re) +
+                double(fb.im) * double(Hb.im);
+        return;
+    }
+    if (a.eta) {
+        Ha = Ha - ej * fa;
+        Hb = Hb - ej * fb;
+    }
     cpx<T> va, vb;   // vector whose densities are accumulated
     if (MODE == KP_APPLY) {
         const cpx<T> oa = coef * Ha, ob = coef * Hb;
@@ -396,6 +413,7 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
 
     for (int jl = jbeg; jl < jend; ++jl) {
         const long long jgl = a.j0 + jl;
+        const T ej = a.eta ? T(a.eta[jgl]) : T(0);
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z0) * (long long)nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z0) * (long long)nxy;
@@ -454,13 +472,13 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
                     Tb = Tb + a.G[lofb + q];
                 }
                 point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
-                                        (long long)z0 * nxy + q, coef, cdt, dn[i], dkr[i], dki[i], ekin);
+                                        (long long)z0 * nxy + q, coef, cdt, ej, dn[i], dkr[i], dki[i], ekin);
             }
             __syncthreads();
         }
     }
-    if (MODE == KP_KINETIC) {
-        // workgroup reduction of the kinetic partial sum
+    if (MODE == KP_KINETIC || MODE == KP_ETA) {
+        // workgroup reduction of the kinetic (or eta) partial sum
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = ekin;
         __syncthreads();
@@ -488,6 +506,17 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
             }
         }
     }
+}
+
+// eta_j = a^3 sum over the nblk plane blocks of qpwf j (fixed order), one
+// thread per qpwf; part[j * nblk + b] comes from the KP_ETA launch (jg = 1).
+__global__ void __launch_bounds__(256) eta_reduce_kernel(const double* __restrict__ part, int nblk, int k,
+                                                         double a3, double* __restrict__ eta) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(long long)j * nblk + b];
+    eta[j] = a3 * s;
 }
 
 // ---------------------------------------------------------------------------

@@ -303,6 +303,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
 
     for (int jl = jbeg; jl < jend; ++jl) {
         const long long jgl = a.j0 + jl;
+        const T ej = a.eta ? T(a.eta[jgl]) : T(0);
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
@@ -372,13 +373,13 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                     }
                     const long long ea = offa + pt, eb = offb + pt;
                     point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
-                                            coef, cdt, dn[q], dkr[q], dki[q], ekin);
+                                            coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
                 }
             }
             __syncthreads();
         }
     }
-    if (MODE == KP_KINETIC) {
+    if (MODE == KP_KINETIC || MODE == KP_ETA) {
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = ekin;
         __syncthreads();

@@ -94,6 +94,7 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
 
     for (int jl = jbeg; jl < jend; ++jl) {
         const long long jgl = a.j0 + jl;
+        const float ej = a.eta ? float(a.eta[jgl]) : 0.0f;
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
@@ -175,14 +176,14 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
                         Tb = Tb + a.G[lofb + pt];
                     }
                     point_epilogue<float, MODE>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt, offb + pt,
-                                                (long long)z * nxy + pt, coef, cdt, dn[u * 4 + r], dkr[u * 4 + r],
+                                                (long long)z * nxy + pt, coef, cdt, ej, dn[u * 4 + r], dkr[u * 4 + r],
                                                 dki[u * 4 + r], ekin);
                 }
             }
             __syncthreads();
         }
     }
-    if (MODE == KP_KINETIC) {
+    if (MODE == KP_KINETIC || MODE == KP_ETA) {
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = ekin;
         __syncthreads();

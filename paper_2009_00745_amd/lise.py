@@ -38,7 +38,8 @@ class Functional(ct.Structure):
                 ("frozen", ct.c_int32), ("regularize", ct.c_int32),
                 ("U0", ct.c_double), ("Delta0_re", ct.c_double), ("Delta0_im", ct.c_double),
                 ("ext_A", ct.c_double), ("ext_w", ct.c_double),
-                ("ext_r0", ct.c_double * 3), ("ext_t_on", ct.c_double)]
+                ("ext_r0", ct.c_double * 3), ("ext_t_on", ct.c_double),
+                ("remove_phase", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class Obs(ct.Structure):
@@ -118,7 +119,8 @@ def functional_struct(f):
     d0 = complex(f.Delta0)
     return Functional(f.ncomp, f.precision, f.mu_up, f.mu_dn, f.beta, f.g, f.w,
                       int(f.frozen), int(getattr(f, "regularize", 0)), f.U0, d0.real, d0.imag,
-                      f.ext_A, f.ext_w, (ct.c_double * 3)(*f.ext_r0), f.ext_t_on)
+                      f.ext_A, f.ext_w, (ct.c_double * 3)(*f.ext_r0), f.ext_t_on,
+                      int(getattr(f, "remove_phase", 0)), 0)
 
 
 def coupling(lattice, functional):

@@ -167,6 +167,51 @@ def test_regularised_coupling_step(lise):
         assert abs(obs["E_pair"] - o["E_pair"]) < 1e-10 * abs(o["E_pair"])
 
 
+def test_phase_removal_step(lise):
+    """Eq. (sp_en) phase removal: FP64 on the fast path (16^3, chunked, overlap) and on
+    the fused path (C = 4, 8^3) against the oracle; FP32 and the bf16x3 MFMA form
+    against the FP64 oracle densities."""
+    cases = [(wl.config2(M=24, n=16), {"chunk_qpwf": 10, "jgroup": 3}, 1e-11),
+             (wl.config4(M=24, n=8, precision=wl.FP64), {}, 1e-11),
+             (wl.config3(M=16, n=20, precision=wl.FP32), {}, 1e-5),
+             (wl.config4(M=12, n=16, precision=wl.FP32_MFMA), {}, 1e-5)]
+    for w, tuning, tol in cases:
+        w.functional.remove_phase = 1
+        prec = w.functional.precision
+        say(f"step {w.name} phase removed (precision {prec}), 12 steps")
+        got, n, k, t, s, obs, ev = run_pair(lise, w, 12, tuning=tuning)
+        n0, k0 = oracle.densities(ev.y, w.functional)
+        e = (rel_l2(n, n0), rel_l2(k, k0))
+        if prec == wl.FP64:
+            e = (rel_l2(got, ev.y),) + e
+        say(f"  rel L2: {e}")
+        assert max(e) < tol
+
+
+def test_phase_removal_frozen_eigenvectors_stay_put(lise):
+    """Frozen fields, plane-wave BdG eigenvectors: with the phase removed y' = 0."""
+    lat = wl.Lattice(16, 16, 16, 1.0)
+    U0, D0, mu = 0.15, 0.4 * np.exp(-0.3j), 0.7
+    fn = wl.Functional(ncomp=2, mu_up=mu, mu_dn=mu, frozen=1, U0=U0, Delta0=D0, g=1.0, remove_phase=1)
+    idx = wl.k_order(lat)[:32]
+    pw = wl.plane_waves(lat, idx)
+    k2 = np.sum(wl.k_of(lat, idx) ** 2, axis=1)
+    ab = []
+    for j in range(32):
+        xi = 0.5 * k2[j] + U0 - mu
+        ab.append(np.linalg.eigh(np.array([[xi, D0], [np.conj(D0), -xi]]))[1][:, j % 2])
+    psi = np.array(ab)[:, :, None, None, None] * pw[:, None]
+    say("frozen eigenvectors, phase removed, 16^3 M = 32, 40 steps")
+    ctx = lise.Context(lat, 32, fn)
+    ctx.set_qpwf(0, psi)
+    ctx.step(0.004, 40)
+    got = ctx.get_qpwf(0, 32)
+    ctx.close()
+    err = float(np.max(np.abs(got - psi)) / np.max(np.abs(psi)))
+    say(f"  max deviation {err:.3e}")
+    assert err < 1e-12
+
+
 def test_four_component_step(lise):
     """C = 4 spin-imbalanced set on 8^3 (FP64), 20 ABM steps."""
     w = wl.config4(M=48, n=8, precision=wl.FP64)

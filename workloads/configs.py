@@ -48,6 +48,7 @@ class Functional:
     ext_w: float = 1.0
     ext_r0: tuple = (0.0, 0.0, 0.0)
     ext_t_on: float = 0.0
+    remove_phase: int = 0
     precision: int = FP64
 
     def as_dict(self):
