@@ -8,4 +8,5 @@ from .lise_oracle import (wavenumbers, dft_matrix, dft3, k_squared, kinetic,
                           hamiltonian_of, rhs, taylor_propagate, series_step,
                           abm_update, Evolver, observables, gram, lattice_K,
                           effective_coupling, quasiparticle_energies, apply_h_shifted,
+                          derivative_matrix, gradient, current_density, kick,
                           ABM_P, ABM_C, ABM_M, ABM_Y)

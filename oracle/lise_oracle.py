@@ -90,6 +90,24 @@ def kinetic(f, lat):
     return dft3(F, +1) / lat.n
 
 
+def derivative_matrix(n, a):
+    """D = F^{-1} diag(i k) F on one axis (Sec. Discretization): the spectral first
+    derivative, with the N/2 mode of an even axis set to zero as the paper does
+    for odd derivatives."""
+    k = wavenumbers(n, a).copy()
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    return dft_matrix(n, +1) @ np.diag(1j * k) @ dft_matrix(n, -1) / n
+
+
+def gradient(f, lat):
+    """(d/dx f, d/dy f, d/dz f) of arrays (..., nz, ny, nx) by dense spectral derivatives."""
+    dx = np.matmul(f, derivative_matrix(lat.nx, lat.a).T)
+    dy = np.matmul(derivative_matrix(lat.ny, lat.a), f)
+    dz = np.einsum("kz,...zyx->...kyx", derivative_matrix(lat.nz, lat.a), f)
+    return dx, dy, dz
+
+
 # ---------------------------------------------------------------------------
 # Densities (Eq. rho_t, nu_t) and potentials (Eq. pairingfield)
 
@@ -113,6 +131,33 @@ def densities(psi, fn):
     else:
         raise ValueError("ncomp must be 2 or 4")
     return n, kappa
+
+
+def current_density(psi, lat, fn):
+    """j(r) = (1 / 2i) sum_k [v_k grad v_k^* - v_k^* grad v_k] = -sum_k Im(v_k^* grad v_k)
+    (Eq. j), over the v components (v for C = 2 with the weight w; v_up and v_dn
+    for C = 4).  Returns an array (3, nz, ny, nx) ordered x, y, z."""
+    if fn.ncomp == 2:
+        vs, wt = [1], fn.w
+    else:
+        vs, wt = [2, 3], 1.0
+    j = np.zeros((3, lat.nz, lat.ny, lat.nx))
+    for c in vs:
+        v = psi[:, c]
+        for ax, dv in enumerate(gradient(v, lat)):
+            j[ax] -= wt * np.sum(np.imag(np.conj(v) * dv), axis=0)
+    return j
+
+
+def kick(psi, chi, fn):
+    """Gauge transformation of Eq. (kick): u -> exp(i chi) u, v -> exp(-i chi) v for
+    every qpwf (C = 2: (u, v); C = 4: (u_up, u_dn, v_up, v_dn))."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    ph = np.exp(1j * np.asarray(chi, dtype=np.float64))
+    nu = 1 if fn.ncomp == 2 else 2
+    out[:, :nu] *= ph
+    out[:, nu:] *= np.conj(ph)
+    return out
 
 
 def external_potential(lat, fn, t):
@@ -398,6 +443,7 @@ def observables(psi, lat, fn, t):
       E_pair = a^3 sum_r g |kappa|^2          (Eq. pairing; g_eff when regularised),
       E_ext  = a^3 sum_r U_ext n.
     <|Delta|> = int |Delta| n / int n; r_cm = int r n / int n.
+    P = int j (total current, Eq. j) and v_cm = P / N (Eq. vel with m = hbar = 1).
     """
     a3 = lat.a ** 3
     n, kappa = densities(psi, fn)
@@ -420,10 +466,11 @@ def observables(psi, lat, fn, t):
            float(np.sum(n * xs[1][None, :, None])) / tot if tot else 0.0,
            float(np.sum(n * xs[2][:, None, None])) / tot if tot else 0.0]
     norms = a3 * np.sum(np.abs(psi) ** 2, axis=(1, 2, 3, 4))
+    P = [a3 * float(np.sum(c)) for c in current_density(psi, lat, fn)]
     return dict(t=t, N=N, E=ekin + e_int + e_pair + e_ext, E_kin=ekin, E_int=e_int,
                 E_pair=e_pair, E_ext=e_ext,
                 mean_abs_delta=float(np.sum(np.abs(Delta) * n)) / tot if tot else 0.0,
-                r_cm=rcm, norms=norms)
+                r_cm=rcm, norms=norms, P=P, v_cm=[p / N if N else 0.0 for p in P])
 
 
 def gram(psi, lat):
