@@ -119,7 +119,8 @@ typedef struct {
  *   E_ext  = a^3 sum_r U_ext n;
  *   mean_abs_delta = sum |Delta| n / sum n;  r_cm = sum r n / sum n;
  *   norm_drift_* = max / mean over j of |<psi_j|psi_j> - <psi_j|psi_j>_0|,
- *   relative to the norms when the qpwfs were last set. */
+ *   relative to the norms when the qpwfs were last set;
+ *   P = a^3 sum_r j(r) with j of lise_current, v_cm = P / N. */
 typedef struct {
     double t;
     int64_t step;
@@ -127,6 +128,8 @@ typedef struct {
     double mean_abs_delta;
     double r_cm[3];
     double norm_drift_max, norm_drift_mean;
+    double P[3];      /* a^3 sum_r j (total current of Eq. j) */
+    double v_cm[3];   /* P / N (Eq. vel, m = hbar = 1) */
 } lise_obs;
 
 /* Launch tuning (0 = library default).
@@ -258,6 +261,25 @@ int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chos
  * the context requiring lise_set_qpwf. */
 int lise_save(lise_ctx *c, const char *path, int32_t with_history);
 int lise_load(lise_ctx *c, const char *path);
+
+/* Boost of Eq. (kick): u -> exp(i chi) u and v -> exp(-i chi) v for every
+ * qpwf (C = 2: u = component 0, v = 1; C = 4: u_up, u_dn = 0, 1 and
+ * v_up, v_dn = 2, 3).  chi holds N float64 in the lattice order (x fastest),
+ * a host or device pointer (chi_is_device).  chi = p.r with p on the
+ * momentum grid gives the system the velocity p.  The ABM history is
+ * dropped: the next lise_step runs the start-up.
+ * Errors: ARG, STATE (qpwfs not set), HIP. */
+int lise_kick(lise_ctx *c, const double *chi, int32_t chi_is_device);
+
+/* Current density of Eq. (j) of the current state,
+ *   j(r) = -weight * sum_j Im(v_j^* grad v_j)
+ * over the v components (C = 2: v with the weight w; C = 4: v_up, v_dn with
+ * weight 1), with spectral first derivatives F^{-1}[i k F v] whose N/2 mode
+ * (even axes) is zeroed, as the paper does for odd derivatives.  j_out: 3N
+ * float64 (j_x, then j_y, then j_z, each in lattice order), host or device.
+ * Errors: ARG, STATE, UNSUPPORTED (xy-plane above 4096 points or an xz-tile
+ * that does not fit in LDS), HIP. */
+int lise_current(lise_ctx *c, double *j_out, int32_t out_is_device);
 
 /* The coupling g that Delta = -g kappa uses for this lattice and functional
  * (g itself, or g_eff when fn->regularize = 1), written to *g_out.  Host-only

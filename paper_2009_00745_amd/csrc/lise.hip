@@ -224,7 +224,9 @@ void set_type_attrs(int lim) {
     const void* g[] = {(const void*)kp_kernel<T, 0, 4>, (const void*)kp_kernel<T, 1, 4>, (const void*)kp_kernel<T, 2, 4>,
                        (const void*)kp_kernel<T, 3, 4>, (const void*)kp_kernel<T, 0, 16>, (const void*)kp_kernel<T, 1, 16>,
                        (const void*)kp_kernel<T, 2, 16>, (const void*)kp_kernel<T, 3, 16>, (const void*)kp_kernel<T, 4, 4>,
-                       (const void*)kp_kernel<T, 4, 16>, (const void*)kz_kernel<T>};
+                       (const void*)kp_kernel<T, 4, 16>, (const void*)kz_kernel<T>,
+                       (const void*)current_xy_kernel<T, 4>, (const void*)current_xy_kernel<T, 16>,
+                       (const void*)current_z_kernel<T, 4>, (const void*)current_z_kernel<T, 16>};
     for (const void* f : g) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
@@ -909,6 +911,73 @@ int norms_t(lise_ctx* c, double* dst) {
     return check_launch(c, "norm_kernel");
 }
 
+// Current density of Eq. (j) of the current state into jdev (3N float64: x, y, z).
+template <typename T>
+int current_t(lise_ctx* c, double* jdev) {
+    const int nx = c->lat.nx, ny = c->lat.ny, nz = c->lat.nz;
+    const long long nxy = (long long)nx * ny;
+    const int cap = c->prec == LISE_FP64 ? 2048 : 4096;
+    int yb = 0;
+    for (int d = ny; d >= 1; --d)
+        if (ny % d == 0 && (long long)d * nx * nz <= cap) { yb = d; break; }
+    const size_t lds_xy = 2 * (size_t)nxy * c->esz;
+    const size_t lds_z = 2 * (size_t)nz * yb * nx * c->esz;
+    if (nxy > 16 * kThreads || yb == 0 || lds_xy > c->lds_limit || lds_z > c->lds_limit)
+        return fail(c, LISE_E_UNSUPPORTED, "current density: lattice %dx%dx%d too large for the LDS kernels", nx, ny, nz);
+    CurArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.C = c->C;
+    a.yb = yb;
+    a.jg = c->jg;
+    a.M = c->M;
+    a.nv = c->C == 2 ? 1 : 2;
+    a.v0 = c->C == 2 ? 1 : 2;
+    a.w = c->C == 2 ? c->fn.w : 1.0;
+    a.px = c->px;
+    a.py = c->py;
+    a.pz = c->pz;
+    a.tw = reinterpret_cast<const cpx<T>*>(c->tw);
+    const double pi = 3.14159265358979323846;
+    a.fx = T(2.0 * pi / (nx * c->lat.a) / nx);
+    a.fy = T(2.0 * pi / (ny * c->lat.a) / ny);
+    a.fz = T(2.0 * pi / (nz * c->lat.a) / nz);
+    a.in = ycur<T>(c);
+    a.jpart = c->dpart;
+    const int nslots = (int)((c->M + c->jg - 1) / c->jg);
+    if (nslots > c->slot_cap) return fail(c, LISE_E_STATE, "partial-sum buffer too small");
+    const long long pz = (long long)nz * yb * nx;
+    if (nxy <= 4 * kThreads)
+        hipLaunchKernelGGL((current_xy_kernel<T, 4>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
+    else
+        hipLaunchKernelGGL((current_xy_kernel<T, 16>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
+    CHK(check_launch(c, "current_xy_kernel"));
+    if (pz <= 4 * kThreads)
+        hipLaunchKernelGGL((current_z_kernel<T, 4>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
+    else
+        hipLaunchKernelGGL((current_z_kernel<T, 16>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
+    CHK(check_launch(c, "current_z_kernel"));
+    const long long n3 = 3 * c->N;
+    hipLaunchKernelGGL(slot_sum_kernel, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       c->stream, c->dpart, nslots, n3, jdev);
+    return check_launch(c, "slot_sum_kernel");
+}
+
+// Eq. (kick) on the current state; chi is a device array of N float64.
+template <typename T>
+int kick_t(lise_ctx* c, const double* chi_dev) {
+    double* phase = c->dens_tmp;   // 2N of its 3N doubles: scratch between steps
+    hipLaunchKernelGGL(phase_kernel, dim3((unsigned)((c->N + kThreads - 1) / kThreads)), dim3(kThreads), 0, c->stream,
+                       chi_dev, c->N, phase);
+    CHK(check_launch(c, "phase_kernel"));
+    const long long total = c->M * c->per;
+    hipLaunchKernelGGL((kick_kernel<T>), dim3(4096), dim3(kThreads), 0, c->stream, ycur<T>(c), phase, c->N, c->C,
+                       c->C == 2 ? 1 : 2, total);
+    return check_launch(c, "kick_kernel");
+}
+
 template <typename T>
 int observables_t(lise_ctx* c, lise_obs* o) {
     CHK(ensure_fields_t<T>(c));
@@ -956,6 +1025,17 @@ int observables_t(lise_ctx* c, lise_obs* o) {
     }
     o->norm_drift_max = mx;
     o->norm_drift_mean = c->M ? mean / c->M : 0.0;
+    // total current and centre-of-mass velocity (Eq. j, Eq. vel with m = hbar = 1)
+    CHK(current_t<T>(c, c->dens_tmp));
+    std::vector<double> jh(3 * c->N);
+    HIPCHK(c, hipMemcpyAsync(jh.data(), c->dens_tmp, jh.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 3; ++k) {
+        double sum = 0.0;
+        for (long long r = 0; r < c->N; ++r) sum += jh[k * c->N + r];
+        o->P[k] = a3 * sum;
+        o->v_cm[k] = o->N != 0.0 ? o->P[k] / o->N : 0.0;
+    }
     return LISE_OK;
 }
 
@@ -1643,6 +1723,35 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
 const char* lise_last_error(const lise_ctx* c) { return c ? c->err : "null context"; }
 
 const char* lise_version(void) { return kVersion; }
+
+int lise_kick(lise_ctx* c, const double* chi, int32_t chi_is_device) {
+    if (!c || !chi) return LISE_E_ARG;
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set");
+    const double* cd = chi;
+    if (!chi_is_device) {
+        HIPCHK(c, hipMemcpyAsync(c->V_tmp, chi, (size_t)c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        cd = c->V_tmp;
+    }
+    int rc = c->prec == LISE_FP64 ? kick_t<double>(c, cd) : kick_t<float>(c, cd);
+    if (rc != LISE_OK) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the state jumped: new densities, and the ABM history restarts
+    c->hist = false;
+    c->dens_valid = false;
+    return LISE_OK;
+}
+
+int lise_current(lise_ctx* c, double* j_out, int32_t out_is_device) {
+    if (!c || !j_out) return LISE_E_ARG;
+    if (c->n_set < c->M) return fail(c, LISE_E_STATE, "qpwfs not fully set");
+    double* dst = out_is_device ? j_out : c->dens_tmp;
+    int rc = c->prec == LISE_FP64 ? current_t<double>(c, dst) : current_t<float>(c, dst);
+    if (rc != LISE_OK) return rc;
+    if (!out_is_device)
+        HIPCHK(c, hipMemcpyAsync(j_out, dst, 3 * (size_t)c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LISE_OK;
+}
 
 int lise_coupling(const lise_lattice* lat, const lise_functional* fn, double* g_out) {
     if (!lat || !fn || !g_out) return LISE_E_ARG;

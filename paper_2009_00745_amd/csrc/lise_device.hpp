@@ -567,6 +567,198 @@ __global__ void __launch_bounds__(256) kz_kernel(const KZArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Boost of Eq. (kick): u -> e^{i chi} u, v -> e^{-i chi} v.  phase[r] holds
+// e^{i chi(r)} in float64; components below nu are u, the rest v.
+
+template <typename T>
+__global__ void __launch_bounds__(256) kick_kernel(cpx<T>* __restrict__ state, const double* __restrict__ phase,
+                                                   long long N, int C, int nu, long long total) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long r = e % N;
+        const int c = (int)((e / N) % C);
+        const double pr = phase[2 * r], pi = (c < nu ? 1.0 : -1.0) * phase[2 * r + 1];
+        const cpx<T> v = state[e];
+        const double vr = double(v.re), vi = double(v.im);
+        state[e] = mk(T(vr * pr - vi * pi), T(vr * pi + vi * pr));
+    }
+}
+
+__global__ void __launch_bounds__(256) phase_kernel(const double* __restrict__ chi, long long N,
+                                                    double* __restrict__ phase) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    double s, c;
+    sincos(chi[r], &s, &c);
+    phase[2 * r] = c;
+    phase[2 * r + 1] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Current density of Eq. (j): j = -w sum_k Im(v_k^* grad v_k) with spectral
+// first derivatives F^{-1}[i k F v] (N/2 mode of an even axis zeroed).  Each
+// workgroup walks jg qpwfs and writes float64 partial sums per slot into
+// jpart[slot][axis][N]; a fixed-order sum over the slots follows.
+
+template <typename T>
+struct CurArgs {
+    int nx, ny, nz, C, yb, jg;
+    long long M;
+    int nv, v0;            // v components: v0 .. v0 + nv - 1
+    double w;
+    AxisPlan px, py, pz;
+    const cpx<T>* tw;
+    T fx, fy, fz;          // 2 pi / (L_a n_a): derivative factor per signed mode
+    const cpx<T>* in;
+    double* jpart;
+};
+
+template <typename T>
+__device__ __forceinline__ T deriv_factor(int m, int n, T f) {
+    return (2 * m == n) ? T(0) : f * T(signed_mode(m, n));
+}
+
+// x and y components from one xy-plane in LDS (PPT points per thread)
+template <typename T, int PPT>
+__global__ void __launch_bounds__(256) current_xy_kernel(const CurArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    const int nxy = a.nx * a.ny;
+    cpx<T>* bufA = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* bufB = bufA + nxy;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int z = blockIdx.x;
+    const long long N = (long long)nxy * a.nz;
+    const long long j0 = (long long)blockIdx.y * a.jg;
+    const long long j1 = min(a.M, j0 + a.jg);
+    const LineMap lmx = {a.ny, a.ny, a.nx, 0, 1, 0};
+    const LineMap lmy = {a.nx, a.nx, 1, 0, a.nx, 1};
+    double jx[PPT], jy[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) jx[i] = jy[i] = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        for (int cv = 0; cv < a.nv; ++cv) {
+            const long long off = ((j * a.C + a.v0 + cv) * a.nz + z) * (long long)nxy;
+            cpx<T> f[PPT];
+            for (int ax = 0; ax < 2; ++ax) {
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const int q = tid + i * nth;
+                    if (q < nxy) {
+                        if (ax == 0) f[i] = a.in[off + q];
+                        bufA[q] = f[i];
+                    }
+                }
+                __syncthreads();
+                const LineMap& lm = ax == 0 ? lmx : lmy;
+                const AxisPlan& pl = ax == 0 ? a.px : a.py;
+                cpx<T>* r = fft_axis<T, false>(bufA, bufB, pl, a.tw, lm, tid, nth);
+                cpx<T>* o = (r == bufA) ? bufB : bufA;
+                for (int e = tid; e < nxy; e += nth) {
+                    const int m = ax == 0 ? e % a.nx : e / a.nx;
+                    const T k = ax == 0 ? deriv_factor<T>(m, a.nx, a.fx) : deriv_factor<T>(m, a.ny, a.fy);
+                    r[e] = mk(-k * r[e].im, k * r[e].re);   // i k F v
+                }
+                __syncthreads();
+                r = fft_axis<T, true>(r, o, pl, a.tw, lm, tid, nth);
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const int q = tid + i * nth;
+                    if (q < nxy) {
+                        const cpx<T> d = r[q];
+                        // Im(conj(f) d)
+                        const double im = double(f[i].re) * double(d.im) - double(f[i].im) * double(d.re);
+                        if (ax == 0) jx[i] -= a.w * im;
+                        else jy[i] -= a.w * im;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    double* base = a.jpart + (long long)blockIdx.y * 3 * N + (long long)z * nxy;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int q = tid + i * nth;
+        if (q < nxy) {
+            base[q] = jx[i];
+            base[N + q] = jy[i];
+        }
+    }
+}
+
+// z component on tiles of yb rows by nz planes (layout [z][row])
+template <typename T, int PPT>
+__global__ void __launch_bounds__(256) current_z_kernel(const CurArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    const int row = a.yb * a.nx;
+    const int P = a.nz * row;
+    cpx<T>* bufA = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* bufB = bufA + P;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const long long nxy = (long long)a.nx * a.ny;
+    const long long N = nxy * a.nz;
+    const int y0 = blockIdx.x * a.yb;
+    const long long j0 = (long long)blockIdx.y * a.jg;
+    const long long j1 = min(a.M, j0 + a.jg);
+    const LineMap lm = {row, row, 1, 0, row, 1};
+    double jz[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) jz[i] = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        for (int cv = 0; cv < a.nv; ++cv) {
+            const long long off = ((j * a.C + a.v0 + cv) * a.nz) * nxy + (long long)y0 * a.nx;
+            cpx<T> f[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int e = tid + i * nth;
+                if (e < P) {
+                    const int zz = e / row, rr = e % row;
+                    f[i] = a.in[off + zz * nxy + rr];
+                    bufA[e] = f[i];
+                }
+            }
+            __syncthreads();
+            cpx<T>* r = fft_axis<T, false>(bufA, bufB, a.pz, a.tw, lm, tid, nth);
+            cpx<T>* o = (r == bufA) ? bufB : bufA;
+            for (int e = tid; e < P; e += nth) {
+                const T k = deriv_factor<T>(e / row, a.nz, a.fz);
+                r[e] = mk(-k * r[e].im, k * r[e].re);
+            }
+            __syncthreads();
+            r = fft_axis<T, true>(r, o, a.pz, a.tw, lm, tid, nth);
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const int e = tid + i * nth;
+                if (e < P) {
+                    const cpx<T> d = r[e];
+                    jz[i] -= a.w * (double(f[i].re) * double(d.im) - double(f[i].im) * double(d.re));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double* base = a.jpart + (long long)blockIdx.y * 3 * N + 2 * N + (long long)y0 * a.nx;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int e = tid + i * nth;
+        if (e < P) {
+            const int zz = e / row, rr = e % row;
+            base[zz * nxy + rr] = jz[i];
+        }
+    }
+}
+
+// out[e] = sum over slots of part[slot][e], e < n3 (fixed order)
+__global__ void __launch_bounds__(256) slot_sum_kernel(const double* __restrict__ part, int nslots, long long n3,
+                                                       double* __restrict__ out) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n3) return;
+    double s = 0.0;
+    for (int k = 0; k < nslots; ++k) s += part[(long long)k * n3 + e];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
 // Densities straight from a state (no Hamiltonian), one thread per point,
 // each thread walking jg qpwfs; partial sums per slot.
 

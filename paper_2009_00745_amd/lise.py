@@ -22,7 +22,7 @@ SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_
            "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
            "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune", "lise_coupling",
-           "lise_save", "lise_load",
+           "lise_save", "lise_load", "lise_kick", "lise_current",
            "lise_batch_create", "lise_batch_step", "lise_batch_last_error", "lise_batch_free"]
 
 
@@ -47,11 +47,13 @@ class Obs(ct.Structure):
                 ("N", ct.c_double), ("E", ct.c_double), ("E_kin", ct.c_double),
                 ("E_int", ct.c_double), ("E_pair", ct.c_double), ("E_ext", ct.c_double),
                 ("mean_abs_delta", ct.c_double), ("r_cm", ct.c_double * 3),
-                ("norm_drift_max", ct.c_double), ("norm_drift_mean", ct.c_double)]
+                ("norm_drift_max", ct.c_double), ("norm_drift_mean", ct.c_double),
+                ("P", ct.c_double * 3), ("v_cm", ct.c_double * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["r_cm"] = list(self.r_cm)
+        for k in ("r_cm", "P", "v_cm"):
+            d[k] = list(getattr(self, k))
         return d
 
 
@@ -94,6 +96,8 @@ def load_library(path=LIB_PATH):
         "lise_version": ([], ct.c_char_p),
         "lise_free": ([P], None),
         "lise_autotune": ([P, ct.c_double, ct.c_int32, ct.POINTER(Tuning)], ct.c_int),
+        "lise_kick": ([P, P, ct.c_int32], ct.c_int),
+        "lise_current": ([P, P, ct.c_int32], ct.c_int),
         "lise_save": ([P, ct.c_char_p, ct.c_int32], ct.c_int),
         "lise_load": ([P, ct.c_char_p], ct.c_int),
         "lise_coupling": ([ct.POINTER(Lattice), ct.POINTER(Functional), ct.POINTER(ct.c_double)], ct.c_int),
@@ -247,6 +251,19 @@ class Context:
         t = Tuning()
         self._check(self.lib.lise_autotune(self._h, dt, trial_steps, ct.byref(t)), "lise_autotune")
         return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def kick(self, chi):
+        """Eq. (kick) with the real phase field chi (shape (nz, ny, nx) or N values)."""
+        chi = np.ascontiguousarray(np.asarray(chi, dtype=np.float64).reshape(-1))
+        if chi.size != self.nx * self.ny * self.nz:
+            raise ValueError("chi must hold one value per lattice point")
+        self._check(self.lib.lise_kick(self._h, chi.ctypes.data, 0), "lise_kick")
+
+    def current(self):
+        """Current density of Eq. (j) as an array (3, nz, ny, nx): j_x, j_y, j_z."""
+        out = np.empty((3, self.nz, self.ny, self.nx), dtype=np.float64)
+        self._check(self.lib.lise_current(self._h, out.ctypes.data, 0), "lise_current")
+        return out
 
     def save(self, path, with_history=True):
         """Write a checkpoint file (with the ABM history: bit-exact continuation)."""

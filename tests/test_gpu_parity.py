@@ -212,6 +212,97 @@ def test_phase_removal_frozen_eigenvectors_stay_put(lise):
     assert err < 1e-12
 
 
+def lattice_chi(lat, p, seed=None, amp=0.0):
+    """chi = p.r, plus a smooth random periodic part when amp > 0."""
+    x = np.arange(lat.nx) * lat.a
+    y = np.arange(lat.ny) * lat.a
+    z = np.arange(lat.nz) * lat.a
+    chi = p[0] * x[None, None, :] + p[1] * y[None, :, None] + p[2] * z[:, None, None]
+    if amp:
+        rng = np.random.default_rng(seed)
+        for _ in range(3):
+            m = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            kx, ky, kz = (2 * np.pi * m[0] / (lat.nx * lat.a), 2 * np.pi * m[1] / (lat.ny * lat.a),
+                          2 * np.pi * m[2] / (lat.nz * lat.a))
+            chi = chi + amp * np.cos(kx * x[None, None, :] + ky * y[None, :, None] + kz * z[:, None, None] + ph)
+    return chi
+
+
+def test_current_density_matches_oracle(lise):
+    """Eq. (j) current and P, v_cm of the observables after a few steps: FP64 (C = 2 on
+    16^3 and 20^3, C = 4 on 8^3) against the oracle; FP32 within 1e-6."""
+    cases = [(wl.config2(M=24, n=16), 1e-12), (wl.config3(M=16, n=20, precision=wl.FP64), 1e-12),
+             (wl.config4(M=24, n=8, precision=wl.FP64), 1e-12),
+             (wl.config3(M=16, n=20, precision=wl.FP32), 1e-6)]
+    for w, tol in cases:
+        say(f"current {w.name} precision {w.functional.precision}: 4 steps")
+        ctx = lise.Context(w.lattice, w.M, w.functional)
+        ctx.set_qpwf(0, w.qpwfs())
+        ctx.step(w.dt, 4)
+        j = ctx.current()
+        obs = ctx.observables()
+        ctx.close()
+        ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
+        ev.step(w.dt, 4)
+        jr = oracle.current_density(ev.y, w.lattice, w.functional)
+        o = oracle.observables(ev.y, w.lattice, w.functional, ev.t)
+        e = rel_l2(j, jr)
+        scale = max(np.max(np.abs(jr)), 1e-300) * w.lattice.a ** 3 * w.lattice.n
+        dP = max(abs(obs["P"][k] - o["P"][k]) for k in range(3)) / scale
+        say(f"  j rel L2 {e:.3e}, P diff / scale {dP:.3e}")
+        assert e < tol and dP < 10 * tol
+
+
+def test_kick_then_step_matches_oracle(lise):
+    """Eq. (kick) with chi = p.r plus a smooth random field, then start-up + 10 ABM
+    steps; C = 2 (16^3, FP64) and C = 4 (8^3, FP64)."""
+    for w in (wl.config2(M=24, n=16), wl.config4(M=24, n=8, precision=wl.FP64)):
+        lat = w.lattice
+        p = np.array([2 * np.pi / (lat.nx * lat.a), 0.0, -2 * np.pi / (lat.nz * lat.a)])
+        chi = lattice_chi(lat, p, seed=3, amp=0.3)
+        say(f"kick {w.name}: 3 steps, kick, 10 steps")
+        ctx = lise.Context(lat, w.M, w.functional)
+        ctx.set_qpwf(0, w.qpwfs())
+        ctx.step(w.dt, 3)
+        ctx.kick(chi)
+        after_kick = ctx.get_qpwf(0, w.M)
+        ctx.step(w.dt, 10)
+        got = ctx.get_qpwf(0, w.M)
+        (t, s) = ctx.time()
+        ctx.close()
+        ev = oracle.Evolver(lat, w.functional, w.qpwfs())
+        ev.step(w.dt, 3)
+        k = oracle.kick(ev.y, chi, w.functional)
+        assert rel_l2(after_kick, k) < 1e-15
+        ev2 = oracle.Evolver(lat, w.functional, k, ev.t)
+        ev2.step_count = ev.step_count
+        ev2.step(w.dt, 10)
+        assert abs(t - ev2.t) < 1e-13 and s == ev2.step_count
+        e = rel_l2(got, ev2.y)
+        say(f"  rel L2 after 10 steps {e:.3e}")
+        assert e < 1e-11
+
+
+def test_boosted_uniform_state_velocity(lise):
+    """Kicked closed-shell uniform BCS state: v_cm = p while it evolves (Galilean covariance)."""
+    lat = wl.Lattice(16, 16, 16, 1.0)
+    fn = wl.Functional(ncomp=2, mu_up=0.8, mu_dn=0.8, beta=0.37, g=2.0, w=2.0)
+    M = 33
+    psi = wl.uniform_bcs(lat, fn, M, 0.45, 0.8)(0, M)
+    p = np.array([2 * np.pi / 16, 0.0, 0.0])
+    say("boosted uniform state 16^3, M = 33, 40 steps")
+    ctx = lise.Context(lat, M, fn)
+    ctx.set_qpwf(0, psi)
+    ctx.kick(lattice_chi(lat, p))
+    v0 = ctx.observables()["v_cm"]
+    ctx.step(0.005, 40)
+    v1 = ctx.observables()["v_cm"]
+    ctx.close()
+    say(f"  v_cm before {v0}, after {v1}")
+    assert np.allclose(v0, p, atol=1e-12) and np.allclose(v1, p, atol=1e-10)
+
+
 def test_four_component_step(lise):
     """C = 4 spin-imbalanced set on 8^3 (FP64), 20 ABM steps."""
     w = wl.config4(M=48, n=8, precision=wl.FP64)
