@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-phase", action="store_true",
+                    help="skip the variant with the trivial phase removed (Eq. sp_en)")
     ap.add_argument("--batched", type=int, default=16,
                     help="number of independent systems in the batched variant (0 = skip; 64 = full workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -223,7 +225,7 @@ def main():
     achieved = (alg_bytes_total / n_plane) / avg_launch_s
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": None,
-                "kernel": "kp_kernel (ABM phases)", "launches": n_plane,
+                "kernel": "plane kernel, ABM phases (kp_fast on 8..64 sides)", "launches": n_plane,
                 "avg_launch_ms": ms_plane / n_plane,
                 "alg_bytes_per_launch": alg_bytes_total / n_plane}
     breakdown = {k: {"launches": n, "ms_per_step": ms / args.steps} for k, (n, ms) in prof.items()}
@@ -257,6 +259,27 @@ def main():
             "after_steps": int(s32),
             "tuning": chosen32,
             "step_hbm_frac": (w32.M * args.steps / el32) * 16 * C * N * 8 / HBM_PEAK}
+
+    if not args.no_phase and args.workload == "cfg2":
+        wp = make_workload("cfg2", M=args.M)
+        wp.functional.remove_phase = 1
+        ctxp, elp, profp = run_gpu(wp, args.steps, args.warmup, tuning if not autotune else None,
+                                   autotune=autotune)
+        chosenp = profp.pop("tuning")
+        n_p, k_p = ctxp.densities()
+        tp, sp = ctxp.time()
+        ctxp.close()
+        assert sp == s_now, (sp, s_now)
+        valp = wp.M * args.steps / elp
+        variants["phase_removed_fp64"] = {
+            "value": valp, "unit": "qpwf-steps/s", "ms_per_step": 1e3 * elp / args.steps,
+            "kernel_ms_per_step": {k: ms / args.steps for k, (n, ms) in profp.items()},
+            "cost_vs_plain": value / valp,
+            "density_rel_l2_vs_plain": {
+                "n": float(np.linalg.norm(n_p - n64) / np.linalg.norm(n64)),
+                "kappa": float(np.linalg.norm(k_p - k64) / np.linalg.norm(k64))},
+            "after_steps": int(sp), "tuning": chosenp,
+            "note": "eta pass re-reads x and the z-term: 24 state arrays per step instead of 20"}
 
     if args.batched and args.workload == "cfg2":
         variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
