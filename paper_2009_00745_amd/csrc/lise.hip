@@ -450,6 +450,17 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     return check_launch(c, "kp_kernel");
 }
 
+template <typename T, int NZ>
+void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st) {
+    constexpr int L = kz_lanes<NZ>();
+    const long long threads = f.ncols * L;
+    dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
+    if constexpr (L > 1)
+        hipLaunchKernelGGL((kz_lanes_kernel<T, NZ, L>), grid, dim3(kThreads), 0, st, f);
+    else
+        hipLaunchKernelGGL((kz_fast<T, NZ>), grid, dim3(kThreads), 0, st, f);
+}
+
 template <typename T>
 int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, hipStream_t st) {
     if (c->fast_z) {
@@ -464,17 +475,16 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
         f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
         f.in = in;
         f.G = reinterpret_cast<cpx<T>*>(Gdst);
-        dim3 grid((unsigned)((f.ncols + kThreads - 1) / kThreads));
         hipEvent_t ev;
         prof_begin(c, 1, &ev, st);
         switch (c->lat.nz) {
-            case 8: hipLaunchKernelGGL((kz_fast<T, 8>), grid, dim3(kThreads), 0, st, f); break;
-            case 16: hipLaunchKernelGGL((kz_fast<T, 16>), grid, dim3(kThreads), 0, st, f); break;
-            case 20: hipLaunchKernelGGL((kz_fast<T, 20>), grid, dim3(kThreads), 0, st, f); break;
-            case 24: hipLaunchKernelGGL((kz_fast<T, 24>), grid, dim3(kThreads), 0, st, f); break;
-            case 32: hipLaunchKernelGGL((kz_fast<T, 32>), grid, dim3(kThreads), 0, st, f); break;
-            case 48: hipLaunchKernelGGL((kz_fast<T, 48>), grid, dim3(kThreads), 0, st, f); break;
-            default: hipLaunchKernelGGL((kz_fast<T, 64>), grid, dim3(kThreads), 0, st, f); break;
+            case 8: launch_kz_fast_n<T, 8>(f, st); break;
+            case 16: launch_kz_fast_n<T, 16>(f, st); break;
+            case 20: launch_kz_fast_n<T, 20>(f, st); break;
+            case 24: launch_kz_fast_n<T, 24>(f, st); break;
+            case 32: launch_kz_fast_n<T, 32>(f, st); break;
+            case 48: launch_kz_fast_n<T, 48>(f, st); break;
+            default: launch_kz_fast_n<T, 64>(f, st); break;
         }
         prof_end(c, 1, ev, st);
         return check_launch(c, "kz_fast");

@@ -259,6 +259,50 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
     for (int z = 0; z < NZ; ++z) dst[z * a.nxy] = x[z];
 }
 
+// z axis with a column split over L adjacent lanes (lane s holds z = s + L q,
+// q < NZ / L): the line transform of the plane kernel (lane_fwd / lane_inv)
+// along z.  A wave reads L contiguous runs of 64 / L columns per load; the
+// column needs NZ / L registers pairs instead of NZ.
+#ifndef LISE_KZ_LANES
+#define LISE_KZ_LANES 1
+#endif
+
+template <int NZ>
+constexpr int kz_lanes() {
+    return (LISE_KZ_LANES > 1 && NZ % LISE_KZ_LANES == 0 && NZ / LISE_KZ_LANES >= 2) ? LISE_KZ_LANES : 1;
+}
+
+template <typename T, int NZ, int L>
+__global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
+    constexpr int P = NZ / L;
+    __shared__ cpx<T> tab[NZ];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long col = t / L;
+    const int s = (int)(t % L);
+    // the L lanes of a column are adjacent and L divides 64: a column is
+    // either wholly inside the launch or wholly outside
+    if (col >= a.ncols) return;
+    const long long jc = col / a.nxy, r = col - jc * a.nxy;
+    const cpx<T>* src = a.in + (a.j0 * a.C + jc) * NZ * a.nxy + r;
+    cpx<T>* dst = a.G + jc * NZ * a.nxy + r;
+    cpx<T> x[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) x[q] = src[(s + L * q) * a.nxy];
+    lane_fwd<T, P, L>(x, tab, s);
+    const int brs = bitrev(s, L);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+        const int kz = k1 + P * brs;
+        const int m = (2 * kz < NZ) ? kz : kz - NZ;
+        x[k1] = (a.cz * T(m * m)) * x[k1];
+    }
+    lane_inv<T, P, L>(x, tab, s);
+#pragma unroll
+    for (int q = 0; q < P; ++q) dst[(s + L * q) * a.nxy] = x[q];
+}
+
 // ---------------------------------------------------------------------------
 // xy planes of a square lattice side N; one workgroup per z-plane and qpwf
 // group, 4N active threads (row = tid/4, lane s = tid%4).
