@@ -129,6 +129,44 @@ def run_batched(nsys, steps, warmup):
             "step_hbm_frac": b_alg / HBM_PEAK}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kp_fast_fp64_32c_traffic.md")
+KERNEL_SOURCES = ("paper_2009_00745_amd/csrc/lise_device.hpp", "paper_2009_00745_amd/csrc/lise_fast.hpp")
+
+
+def measured_traffic():
+    """Per-qpwf HBM traffic of the ABM plane kernels from the committed PMC summary, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        line = [ln for ln in open(TRAFFIC_PROFILE) if ln.startswith("TRAFFIC_JSON ")][0]
+    except (OSError, IndexError):
+        return None
+    rec = json.loads(line[len("TRAFFIC_JSON "):])
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec if h.hexdigest()[:16] == rec["source_hash"] else None
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=3):
+    """Read + write bandwidth of a plain device-to-device copy (torch), best of reps."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        best = t if best is None else min(best, t)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best
+
+
 def cpu_baseline(w_name, M_sample, steps):
     """The oracle, unchanged, on M_sample qpwfs of the same workload."""
     import oracle
@@ -223,8 +261,14 @@ def main():
     alg_bytes_total = args.steps * w.M * b_alg
     avg_launch_s = ms_plane / n_plane / 1e3
     achieved = (alg_bytes_total / n_plane) / avg_launch_s
+    traffic = None
+    rec = measured_traffic() if (w.lattice.nx, w.lattice.ny, w.lattice.nz, C, esz) == (32, 32, 32, 2, 16) else None
+    if rec:
+        qpwf_per_launch = args.steps * w.M * 2 / n_plane
+        traffic = 0.5 * (rec["abm1_bytes_per_qpwf"] + rec["abm2_bytes_per_qpwf"]) * qpwf_per_launch
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": traffic,
+                "measured_copy_GBps": copy_bandwidth() / 1e9,
                 "kernel": "plane kernel, ABM phases (kp_fast on 8..64 sides)", "launches": n_plane,
                 "avg_launch_ms": ms_plane / n_plane,
                 "alg_bytes_per_launch": alg_bytes_total / n_plane}
