@@ -207,6 +207,7 @@ def main():
     ap.add_argument("--M", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--jgroup", type=int, default=0)
+    ap.add_argument("--no-overlap", action="store_true", help="z kernel on the same stream as the plane kernel")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16)
@@ -245,8 +246,8 @@ def main():
 
     w = make_workload(args.workload, M=args.M)
     tuning = {}
-    if args.chunk or args.jgroup:
-        tuning = {"chunk_qpwf": args.chunk, "jgroup": args.jgroup}
+    if args.chunk or args.jgroup or args.no_overlap:
+        tuning = {"chunk_qpwf": args.chunk, "jgroup": args.jgroup, "no_overlap": int(args.no_overlap)}
     C, N = w.functional.ncomp, w.lattice.n
     esz = 16 if w.functional.precision == 0 else 8
     autotune = not args.no_autotune and not tuning

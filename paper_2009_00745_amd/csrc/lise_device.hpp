@@ -300,22 +300,46 @@ struct KPArgs {
 // phase removal on (a.eta set) the other modes apply H - eta_j (ej) instead
 // of H.
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool HASG>
 __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
-                                               long long ea, long long eb, long long rpt, cpx<T> coef, T cdt, T ej,
+                                               long long ea, long long eb, long long rpt, long long ga, long long gb,
+                                               cpx<T> coef, T cdt, T ej,
                                                double& dn, double& dkr, double& dki, double& ekin) {
-    if (MODE == KP_KINETIC) {
+    // Every load of the point is issued before any arithmetic, so that one
+    // round trip to memory serves the z-term, the fields and the ABM history.
+    cpx<T> Ga = mk(T(0), T(0)), Gb = mk(T(0), T(0));
+    if constexpr (HASG) {
+        Ga = a.G[ga];
+        Gb = a.G[gb];
+    }
+    if constexpr (MODE == KP_KINETIC) {
+        Tb = Tb + Gb;
         ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
         return;
     }
+    const double Vd = a.V[rpt];
+    const double Dre = a.D[2 * rpt], Dim = a.D[2 * rpt + 1];
+    cpx<T> h1a, h1b, h2a, h2b, h3a, h3b, h4a, h4b, h5a, h5b;
+    if constexpr (MODE == KP_ABM1) {
+        h1a = a.a1[ea]; h1b = a.a1[eb];
+        h2a = a.a2[ea]; h2b = a.a2[eb];
+        h3a = a.a3[ea]; h3b = a.a3[eb];
+        h4a = a.a4[ea]; h4b = a.a4[eb];
+        h5a = a.a5[ea]; h5b = a.a5[eb];
+    } else if constexpr (MODE == KP_ABM2) {
+        h1a = a.a1[ea]; h1b = a.a1[eb];
+        h5a = a.a5[ea]; h5b = a.a5[eb];
+    }
+    Ta = Ta + Ga;
+    Tb = Tb + Gb;
     const T sg = T(a.sgn[pr]);
-    const T Vr = T(a.V[rpt]);
-    const cpx<T> Dl = mk(sg * T(a.D[2 * rpt]), sg * T(a.D[2 * rpt + 1]));
+    const T Vr = T(Vd);
+    const cpx<T> Dl = mk(sg * T(Dre), sg * T(Dim));
     const T mua = T(a.mu_a[pr]), mub = T(a.mu_b[pr]);
     // H u = (h - mu_a) u + s Delta v ;  H v = s Delta^* u - (h - mu_b) v
     cpx<T> Ha = Ta + (Vr - mua) * fa + Dl * fb;
     cpx<T> Hb = conjg(Dl) * fa - (Tb + (Vr - mub) * fb);
-    if (MODE == KP_ETA) {
+    if constexpr (MODE == KP_ETA) {
         ekin += double(fa.re) * double(Ha.re) + double(fa.im) * double(Ha.im) + double(fb.re) * double(Hb.re) +
                 double(fb.im) * double(Hb.im);
         return;
@@ -325,7 +349,7 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
         Hb = Hb - ej * fb;
     }
     cpx<T> va, vb;   // vector whose densities are accumulated
-    if (MODE == KP_APPLY) {
+    if constexpr (MODE == KP_APPLY) {
         const cpx<T> oa = coef * Ha, ob = coef * Hb;
         if (a.deriv) {
             a.deriv[ea] = mk(Ha.im, -Ha.re);
@@ -345,18 +369,15 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
             a.out[ea] = oa;
             a.out[eb] = ob;
         }
-    } else if (MODE == KP_ABM1) {
+    } else if constexpr (MODE == KP_ABM1) {
         const cpx<T> da = mk(Ha.im, -Ha.re), db = mk(Hb.im, -Hb.re);   // y'_n = -i H y_n
-        const cpx<T> sa = T(0.5) * (fa + a.a1[ea]), sb = T(0.5) * (fb + a.a1[eb]);
-        const cpx<T> d1a = a.a2[ea], d1b = a.a2[eb];
-        const cpx<T> d2a = a.a3[ea], d2b = a.a3[eb];
-        const cpx<T> d3a = a.a4[ea], d3b = a.a4[eb];
-        const cpx<T> Ya = cdt * (T(68) * da - T(102) * d1a + T(68) * d2a - T(17) * d3a);
-        const cpx<T> Yb = cdt * (T(68) * db - T(102) * d1b + T(68) * d2b - T(17) * d3b);
-        const cpx<T> ca = sa + cdt * (T(51) * da + T(3) * d1a + d2a);
-        const cpx<T> cb = sb + cdt * (T(51) * db + T(3) * d1b + d2b);
-        va = (ca + Ya) - T(161.0 / 170.0) * a.a5[ea];   // m = p - 161/170 d_n
-        vb = (cb + Yb) - T(161.0 / 170.0) * a.a5[eb];
+        const cpx<T> sa = T(0.5) * (fa + h1a), sb = T(0.5) * (fb + h1b);
+        const cpx<T> Ya = cdt * (T(68) * da - T(102) * h2a + T(68) * h3a - T(17) * h4a);
+        const cpx<T> Yb = cdt * (T(68) * db - T(102) * h2b + T(68) * h3b - T(17) * h4b);
+        const cpx<T> ca = sa + cdt * (T(51) * da + T(3) * h2a + h3a);
+        const cpx<T> cb = sb + cdt * (T(51) * db + T(3) * h2b + h3b);
+        va = (ca + Ya) - T(161.0 / 170.0) * h5a;   // m = p - 161/170 d_n
+        vb = (cb + Yb) - T(161.0 / 170.0) * h5b;
         a.a6[ea] = da;
         a.a6[eb] = db;
         a.a4[ea] = va;
@@ -366,9 +387,9 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
     } else {   // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = d_n -> d_{n+1}
         const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
         const T k = T(17) * cdt;
-        const cpx<T> ra = a.a1[ea] - k * ma, rb = a.a1[eb] - k * mb;   // d_{n+1}
-        va = fa + T(161.0 / 170.0) * (a.a5[ea] - ra);                    // y_{n+1}
-        vb = fb + T(161.0 / 170.0) * (a.a5[eb] - rb);
+        const cpx<T> ra = h1a - k * ma, rb = h1b - k * mb;             // d_{n+1}
+        va = fa + T(161.0 / 170.0) * (h5a - ra);                        // y_{n+1}
+        vb = fb + T(161.0 / 170.0) * (h5b - rb);
         a.a1[ea] = va;
         a.a1[eb] = vb;
         a.a5[ea] = ra;
@@ -466,13 +487,15 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
             for (int i = 0; i < PPT; ++i) {
                 const int q = tid + i * nth;
                 if (q >= P) continue;
-                cpx<T> Ta = r[q], Tb = r[P + q];
-                if (!a.fused) {
-                    Ta = Ta + a.G[lofa + q];
-                    Tb = Tb + a.G[lofb + q];
-                }
-                point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
-                                        (long long)z0 * nxy + q, coef, cdt, ej, dn[i], dkr[i], dki[i], ekin);
+                const cpx<T> Ta = r[q], Tb = r[P + q];
+                if (a.fused)
+                    point_epilogue<T, MODE, false>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
+                                                   (long long)z0 * nxy + q, 0, 0, coef, cdt, ej, dn[i], dkr[i],
+                                                   dki[i], ekin);
+                else
+                    point_epilogue<T, MODE, true>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
+                                                  (long long)z0 * nxy + q, lofa + q, lofb + q, coef, cdt, ej, dn[i],
+                                                  dkr[i], dki[i], ekin);
             }
             __syncthreads();
         }

@@ -410,14 +410,10 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const int pt = row * N + s + L * q;
-                    cpx<T> Ta = xa[q], Tb = xb[q];
-                    if (!a.fused) {
-                        Ta = Ta + a.G[lofa + pt];
-                        Tb = Tb + a.G[lofb + pt];
-                    }
+                    // the plane kernels never run fused: the z-term is always in G
                     const long long ea = offa + pt, eb = offb + pt;
-                    point_epilogue<T, MODE>(a, pr, Ta, Tb, fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
-                                            coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
+                    point_epilogue<T, MODE, true>(a, pr, xa[q], xb[q], fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
+                                                  lofa + pt, lofb + pt, coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
                 }
             }
             __syncthreads();

@@ -170,14 +170,10 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
                 for (int r = 0; r < 4; ++r) {
                     const int y = 16 * ty + lk + r, x = 16 * (tx0 + u) + li;
                     const int pt = y * N + x;
-                    cpx<float> Ta = mk(ar[u][r], ai[u][r]), Tb = mk(br[u][r], bi[u][r]);
-                    if (!a.fused) {
-                        Ta = Ta + a.G[lofa + pt];
-                        Tb = Tb + a.G[lofb + pt];
-                    }
-                    point_epilogue<float, MODE>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt, offb + pt,
-                                                (long long)z * nxy + pt, coef, cdt, ej, dn[u * 4 + r], dkr[u * 4 + r],
-                                                dki[u * 4 + r], ekin);
+                    const cpx<float> Ta = mk(ar[u][r], ai[u][r]), Tb = mk(br[u][r], bi[u][r]);
+                    point_epilogue<float, MODE, true>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt,
+                                                      offb + pt, (long long)z * nxy + pt, lofa + pt, lofb + pt, coef,
+                                                      cdt, ej, dn[u * 4 + r], dkr[u * 4 + r], dki[u * 4 + r], ekin);
                 }
             }
             __syncthreads();
