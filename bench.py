@@ -43,13 +43,48 @@ def make_workload(name, M=None):
         return w
     if name == "cfg1":
         return wl.config1(M=M)
+    if name == "cfg3":
+        return wl.config3(M=M)                      # 48^3 vortex, FP32 bulk + FP64 sums
+    if name == "cfg4":
+        return wl.config4(M=M)                      # 64^3, C = 4, bf16x3 MFMA xy-kinetic term
+    if name == "cfg4_fp32":
+        w = wl.config4(M=M, precision=wl.FP32)      # same, FP32 register FFTs
+        w.name = w.name + "_stockham"
+        return w
     raise ValueError(name)
 
 
-def upload(ctx, w, piece=512):
-    for j0 in range(0, w.M, piece):
-        k = min(piece, w.M - j0)
-        ctx.set_qpwf(j0, np.ascontiguousarray(w.qpwfs(j0, k)))
+_POOL = None
+
+
+def start_pool():
+    """Host threads for the seeded inputs (numpy releases the GIL in its array loops)."""
+    global _POOL
+    from concurrent.futures import ThreadPoolExecutor
+    n = min(16, len(os.sched_getaffinity(0)))
+    if n > 1:
+        _POOL = ThreadPoolExecutor(max_workers=n)
+
+
+def upload(ctx, w, piece=None):
+    per_qpwf = w.functional.ncomp * w.lattice.n * 16
+    if piece is None:
+        piece = max(1, min(512, (64 << 20) // per_qpwf))
+    ranges = [(j0, min(piece, w.M - j0)) for j0 in range(0, w.M, piece)]
+    if _POOL is None:
+        for j0, k in ranges:
+            ctx.set_qpwf(j0, np.ascontiguousarray(w.qpwfs(j0, k)))
+        return
+    # generate ahead on the pool, upload in order; at most 2x workers pieces in flight
+    futs = {}
+    nxt = 0
+    depth = 2 * _POOL._max_workers
+    for i, (j0, k) in enumerate(ranges):
+        while nxt < len(ranges) and nxt < i + depth:
+            jj, kk = ranges[nxt]
+            futs[nxt] = _POOL.submit(lambda a, b: np.ascontiguousarray(w.qpwfs(a, b)), jj, kk)
+            nxt += 1
+        ctx.set_qpwf(j0, futs.pop(i).result())
 
 
 def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
@@ -226,6 +261,7 @@ def main():
               "multi-GPU sharding over qpwfs is a design note, not a run (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    start_pool()
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -353,6 +389,8 @@ def main():
         "host": platform.node(),
     }
     print(json.dumps(out), flush=True)
+    if _POOL is not None:
+        _POOL.shutdown(wait=False)
 
 
 if __name__ == "__main__":

@@ -16,14 +16,20 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 
 def splitmix64(x):
-    """SplitMix64 output function applied elementwise to uint64 input."""
-    x = np.asarray(x, dtype=np.uint64)
+    """SplitMix64 output function applied elementwise to uint64 input (in place on a copy)."""
+    z = np.array(x, dtype=np.uint64, copy=True)
+    t = np.empty_like(z)
     with np.errstate(over="ignore"):
-        z = x + _GAMMA
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-        z = z ^ (z >> np.uint64(31))
-    return z
+        z += _GAMMA
+        np.right_shift(z, np.uint64(30), out=t)
+        z ^= t
+        z *= _M1
+        np.right_shift(z, np.uint64(27), out=t)
+        z ^= t
+        z *= _M2
+        np.right_shift(z, np.uint64(31), out=t)
+        z ^= t
+    return z[()] if z.ndim == 0 else z
 
 
 def key(*fields):
