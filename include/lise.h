@@ -51,7 +51,14 @@ typedef struct lise_ctx lise_ctx;
 /* Periodic lattice of nx*ny*nz points with spacing a (Sec. Discretization:
  * x_n = n a, n = 0..N-1; momenta k_n = 2 pi n / L for n < N/2 and
  * 2 pi (n - N) / L otherwise, L = N a).  Each of nx, ny, nz must factor into
- * 2, 3 and 5 only and lie in [1, 128]. */
+ * 2, 3 and 5 only and lie in [1, 128].  In addition one xy-plane of both
+ * components of a pair must fit the plane kernel: square planes of side 8,
+ * 16, 20, 24, 32, 48 or 64 always do; other planes need nx*ny <= 2560 points
+ * (LISE_FP64) or <= 4096 (LISE_FP32), and an nz x nx tile must fit the
+ * z-axis kernel (nz*nx <= 5120 for LISE_FP64, 10240 for LISE_FP32, unless nz
+ * is one of the sides above).  lise_init returns LISE_E_UNSUPPORTED
+ * otherwise.  (LISE_FP64 planes of side 64 run with register spills: a
+ * 64-point line over 16 lanes leaves 128 registers per thread.) */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t reserved;

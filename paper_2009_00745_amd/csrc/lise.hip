@@ -267,22 +267,23 @@ int configure(lise_ctx* c) {
         for (int d = 1; d <= nz; ++d)
             if (nz % d == 0 && d * nxy >= kThreads && kp_lds_bytes(c, d) <= c->lds_limit) { zb = d; break; }
         c->zb = zb;
-        if (kp_lds_bytes(c, zb) > c->lds_limit)
-            return fail(c, LISE_E_UNSUPPORTED, "xy-plane %dx%d does not fit in LDS (%zu > %zu bytes)", nx, ny,
-                        kp_lds_bytes(c, zb), c->lds_limit);
         int yb = 1;
         for (int d = ny; d >= 1; --d)
             if (ny % d == 0 && (long long)d * nx * nz <= (c->prec == LISE_FP64 ? 2048 : 4096) &&
                 kz_lds_bytes(c, d) <= c->lds_limit) { yb = d; break; }
         c->yb = yb;
-        if (kz_lds_bytes(c, yb) > c->lds_limit)
-            return fail(c, LISE_E_UNSUPPORTED, "xz-tile does not fit in LDS");
     }
     c->mfma_xy = c->mfma_mode && !c->fused && nx == ny && mfma_side(nx) && c->dkin;
     c->fast_xy = !c->mfma_xy && !c->fused && !c->generic && nx == ny && fast_side(nx) &&
                  fast_kp_lds(c) <= c->lds_limit && c->tw_full_xy >= 0;
     c->fast_z = !c->fused && !c->generic && fast_side(nz) && c->tw_full_z >= 0;
     if (c->fast_xy || c->mfma_xy) c->zb = 1;
+    // the generic LDS kernels must fit where they are the ones that run
+    if (!c->fused && !c->fast_xy && !c->mfma_xy && kp_lds_bytes(c, c->zb) > c->lds_limit)
+        return fail(c, LISE_E_UNSUPPORTED, "xy-plane %dx%d does not fit in LDS (%zu > %zu bytes)", nx, ny,
+                    kp_lds_bytes(c, c->zb), c->lds_limit);
+    if (!c->fused && !c->fast_z && kz_lds_bytes(c, c->yb) > c->lds_limit)
+        return fail(c, LISE_E_UNSUPPORTED, "xz-tile %dx%d does not fit in LDS", nz, nx);
     const long long P = (long long)c->zb * nxy;
     const long long ppt = (P + kThreads - 1) / kThreads;
     if (ppt > 16) return fail(c, LISE_E_UNSUPPORTED, "plane stack of %lld points exceeds 16 per thread", P);

@@ -559,6 +559,32 @@ def test_checkpoint_qpwfs_only_restarts_like_the_oracle(lise, tmp_path):
     assert ck["history"] == 0 and ck["dens"] is None and len(ck["arrays"]) == 1
 
 
+def test_plane_size_limits(lise):
+    """Planes beyond the plane kernel's capacity are refused with UNSUPPORTED; the largest
+    supported shapes run (64 x 64 FP64 on the register-FFT path, 50 x 50 FP64 and
+    80 x 50 FP32 on the LDS path)."""
+    fn64 = wl.Functional(ncomp=2, mu_up=0.5, mu_dn=0.5, beta=0.37, g=1.0)
+    fn32 = wl.Functional(ncomp=2, mu_up=0.5, mu_dn=0.5, beta=0.37, g=1.0, precision=wl.FP32)
+    for (nx, ny, nz), fn in (((80, 80, 4), fn64), ((80, 60, 2), fn32)):
+        say(f"unsupported plane {nx}x{ny}x{nz} precision {fn.precision}")
+        with pytest.raises(lise.LiseError, match="UNSUPPORTED"):
+            lise.Context(wl.Lattice(nx, ny, nz, 1.0), 2, fn)
+    for (nx, ny, nz), fn in (((64, 64, 4), fn64), ((50, 50, 2), fn64), ((80, 50, 2), fn32)):
+        lat = wl.Lattice(nx, ny, nz, 1.0)
+        say(f"largest planes {nx}x{ny}x{nz} precision {fn.precision}: apply H vs oracle")
+        psi = random_state(lat, 2, 2, seed=nx + ny)
+        ctx = lise.Context(lat, 2, fn)
+        ctx.set_qpwf(0, psi)
+        got = ctx.apply_h(0, 2)
+        n, k = ctx.densities()
+        ctx.close()
+        n0, k0 = oracle.densities(psi, fn)
+        V, D = oracle.potentials(n0, k0, lat, fn, 0.0)
+        ref = oracle.apply_h(psi, V, D, lat, fn)
+        tol = 1e-12 if fn.precision == wl.FP64 else 3e-6
+        assert rel_max(got, ref) < tol
+
+
 def test_checkpoint_errors(lise, tmp_path):
     w = wl.config1(M=16)
     path = str(tmp_path / "e.ckpt")
