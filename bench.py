@@ -261,6 +261,9 @@ def main():
               "multi-GPU sharding over qpwfs is a design note, not a run (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    # the batched leg runs one stream per system; HIP maps streams onto this many
+    # hardware queues (default 4), read when HIP initialises
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     start_pool()
     import torch
     if not torch.cuda.is_available():
