@@ -238,7 +238,8 @@ int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *tot
 /* Timed search over launch tuning (chunk size, qpwfs per plane workgroup,
  * z-kernel overlap) for this system: each candidate runs one untimed and
  * `trial_steps` timed ABM steps with step size dt on the live state (the
- * state advances; results change only in rounding), the fastest is kept and
+ * state advances; results change only in rounding); the three fastest run
+ * again over 2 * trial_steps and the fastest of that round is kept and
  * written to *chosen (may be NULL).  Runs the start-up first if needed.
  * Errors: ARG, STATE, HIP, NAN. */
 int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);

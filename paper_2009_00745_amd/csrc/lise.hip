@@ -1695,8 +1695,22 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    lise_tuning best{};
-    float best_ms = 1e30f;
+    // time nsteps of the candidate t (after one untimed step in its shape)
+    auto trial = [&](const lise_tuning& t, int nsteps, float* ms) {
+        int r = lise_set_tuning(c, &t);
+        if (r == LISE_OK) r = lise_step(c, dt, 1);
+        if (r != LISE_OK) return r;
+        (void)hipEventRecord(e0, c->stream);
+        r = lise_step(c, dt, nsteps);
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        *ms = 0.0f;
+        (void)hipEventElapsedTime(ms, e0, e1);
+        return r;
+    };
+    // round 1: every candidate; round 2: the three fastest again over twice the
+    // steps, so that timing noise between close candidates does not decide
+    std::vector<std::pair<float, lise_tuning>> timed;
     int rc = LISE_OK;
     for (long long ch : chunks)
         for (int jg : jgs)
@@ -1709,20 +1723,24 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
                 t.generic = c->generic;
                 t.no_overlap = nov;
                 t.graph = c->use_graph;
-                rc = lise_set_tuning(c, &t);
-                if (rc == LISE_OK) rc = lise_step(c, dt, 1);
-                if (rc != LISE_OK) break;
-                (void)hipEventRecord(e0, c->stream);
-                rc = lise_step(c, dt, trial_steps);
-                (void)hipEventRecord(e1, c->stream);
-                (void)hipEventSynchronize(e1);
                 float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (rc == LISE_OK && ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
-                }
+                rc = trial(t, trial_steps, &ms);
+                if (rc == LISE_OK) timed.push_back({ms, t});
             }
+    lise_tuning best{};
+    if (rc == LISE_OK && !timed.empty()) {
+        std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+        best = timed[0].second;
+        float best_ms = 1e30f;
+        for (size_t i = 0; i < std::min<size_t>(3, timed.size()) && rc == LISE_OK; ++i) {
+            float ms = 0.0f;
+            rc = trial(timed[i].second, 2 * trial_steps, &ms);
+            if (rc == LISE_OK && ms < best_ms) {
+                best_ms = ms;
+                best = timed[i].second;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != LISE_OK) return rc;
