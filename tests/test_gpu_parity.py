@@ -585,6 +585,81 @@ def test_plane_size_limits(lise):
         assert rel_max(got, ref) < tol
 
 
+def test_checkpoint_with_options_continues_bitwise(lise, tmp_path):
+    """Phase removal and the regularised coupling together, on the bf16x3 MFMA form (C = 4,
+    16^3): save with history, reload, continue bit for bit."""
+    w = wl.config4(M=12, n=16, precision=wl.FP32_MFMA)
+    w.functional.remove_phase = 1
+    w.functional.regularize = 1
+    path = str(tmp_path / "opts.ckpt")
+    say("checkpoint MFMA C=4 with phase removal and g_eff: 5 steps, save, 6 more; reload, 6")
+    a = lise.Context(w.lattice, w.M, w.functional)
+    a.set_qpwf(0, w.qpwfs())
+    a.step(w.dt, 5)
+    a.save(path)
+    a.step(w.dt, 6)
+    ya, ta = a.get_qpwf(0, w.M), a.time()
+    a.close()
+    b = lise.Context(w.lattice, w.M, w.functional)
+    b.load(path)
+    b.step(w.dt, 6)
+    yb, tb = b.get_qpwf(0, w.M), b.time()
+    b.close()
+    assert ta == tb and np.array_equal(ya, yb)
+
+
+def test_kick_and_current_fp32_four_components(lise):
+    """FP32 C = 4 (16^3): kick, then the current of Eq. (j) against the oracle's of the
+    kicked FP64 state (FP32 rounding of the state only)."""
+    w = wl.config4(M=12, n=16, precision=wl.FP32)
+    lat = w.lattice
+    p = np.array([0.0, 2 * np.pi / (lat.ny * lat.a), 0.0])
+    chi = lattice_chi(lat, p, seed=9, amp=0.2)
+    say("FP32 C=4 16^3: kick and current")
+    ctx = lise.Context(lat, w.M, w.functional)
+    ctx.set_qpwf(0, w.qpwfs())
+    ctx.kick(chi)
+    j = ctx.current()
+    obs = ctx.observables()
+    ctx.close()
+    k = oracle.kick(w.qpwfs(), chi, w.functional)
+    jr = oracle.current_density(k, lat, w.functional)
+    o = oracle.observables(k, lat, w.functional, 0.0)
+    e = rel_l2(j, jr)
+    say(f"  j rel L2 {e:.3e}, v_cm {obs['v_cm']} vs {o['v_cm']}")
+    assert e < 1e-5
+    assert np.allclose(obs["v_cm"], o["v_cm"], rtol=1e-5, atol=1e-9)
+
+
+def test_batch_with_options_matches_individual(lise):
+    """A batch mixing phase removal, the regularised coupling and plain systems equals
+    stepping each alone (per-system graphs on), bit for bit."""
+    ws = [wl.config2(M=16, n=16), wl.config3(M=12, n=20, precision=wl.FP32), wl.config1(M=32)]
+    ws[0].functional.remove_phase = 1
+    ws[1].functional.regularize = 1
+    dt = 0.002
+    say("batch with options: 3 systems, 9 steps")
+    ctxs = []
+    for w in ws:
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_tuning(graph=1)
+        c.set_qpwf(0, w.qpwfs())
+        ctxs.append(c)
+    b = lise.Batch(ctxs)
+    b.step(dt, 9)
+    got = [c.get_qpwf(0, w.M) for c, w in zip(ctxs, ws)]
+    b.close()
+    for c in ctxs:
+        c.close()
+    for w, g in zip(ws, got):
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_qpwf(0, w.qpwfs())
+        c.step(dt, 9)
+        ref = c.get_qpwf(0, w.M)
+        c.close()
+        assert np.array_equal(g, ref), w.name
+
+
 def test_checkpoint_errors(lise, tmp_path):
     w = wl.config1(M=16)
     path = str(tmp_path / "e.ckpt")
