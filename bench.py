@@ -124,9 +124,9 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     return ctx, t2 - t1, prof
 
 
-def run_batched(nsys, steps, warmup):
+def run_batched(nsys, steps, warmup, graph=1):
     """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced together,
-    each on its own forked stream with its own four-step graph replays."""
+    each on its own forked stream (with its own four-step graph replays when graph = 1)."""
     import torch
     import workloads as wl
     import paper_2009_00745_amd as lise
@@ -136,6 +136,8 @@ def run_batched(nsys, steps, warmup):
     t0 = time.time()
     for w in systems:
         c = lise.Context(w.lattice, w.M, w.functional, stream=stream)
+        if graph:
+            c.set_tuning(graph=1)
         upload(c, w)
         ctxs.append(c)
     log(f"batched: {nsys} systems uploaded in {time.time() - t0:.1f}s")
