@@ -206,10 +206,13 @@ __device__ __forceinline__ void lane_inv(cpx<T>* x, const cpx<T>* __restrict__ t
 #ifndef LISE_PLANE_MAXP_F64
 #define LISE_PLANE_MAXP_F64 2
 #endif
+#ifndef LISE_PLANE_MAXP_F32
+#define LISE_PLANE_MAXP_F32 4
+#endif
 
 template <typename T, int N>
 constexpr int plane_lanes() {
-    constexpr int maxp = sizeof(T) == 8 ? LISE_PLANE_MAXP_F64 : 4;
+    constexpr int maxp = sizeof(T) == 8 ? LISE_PLANE_MAXP_F64 : LISE_PLANE_MAXP_F32;
     int L = 4;
     while (N / L > maxp && L < 16 && N % (2 * L) == 0) L *= 2;
     return L;
