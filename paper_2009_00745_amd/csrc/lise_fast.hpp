@@ -200,14 +200,14 @@ __device__ __forceinline__ void lane_inv(cpx<T>* x, const cpx<T>* __restrict__ t
     RegFft<T, P, L, true>::run(x, tab);
 }
 
-// lanes per line of the plane kernel: enough that a lane holds at most 4
-// points of a line (2 in float64, whose registers limit the waves per SIMD:
-// 32 x 32 planes measured 2.5% faster), capped at 16
+// lanes per line of the plane kernel: enough that a lane holds at most 2
+// points of a line where the side allows, capped at 16 (more waves per SIMD:
+// 32 x 32 planes measured 2.5% faster in float64, 15% in float32 than 4 points)
 #ifndef LISE_PLANE_MAXP_F64
 #define LISE_PLANE_MAXP_F64 2
 #endif
 #ifndef LISE_PLANE_MAXP_F32
-#define LISE_PLANE_MAXP_F32 4
+#define LISE_PLANE_MAXP_F32 2
 #endif
 
 template <typename T, int N>
