@@ -100,6 +100,8 @@ struct lise_ctx {
     double* eta = nullptr;     // [M] eta_j of the vector the current H application acts on
     double* eta_part = nullptr;  // [chunk][plane blocks] partial sums of the eta pass
     long long eta_part_cap = 0;
+    double* ez_part[2] = {nullptr, nullptr};  // z-kinetic partials of the eta pass, per G buffer
+    long long ez_cap = 0;
     bool hist = false;
     bool norms0_valid = false;
     double dt_hist = 0.0;
@@ -210,6 +212,7 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 template <typename T>
@@ -325,6 +328,16 @@ int configure(lise_ctx* c) {
             c->eta_part_cap = need;
         }
         if (!c->eta) CHK(dalloc(c, reinterpret_cast<void**>(&c->eta), (size_t)c->M * sizeof(double)));
+        if (c->fast_xy && c->fast_z) {
+            const long long nez = c->chunk * (long long)c->C * nxy * kz_lanes_of(nz);
+            if (c->ez_cap < nez) {
+                for (int b = 0; b < 2; ++b) {
+                    dfree(reinterpret_cast<void**>(&c->ez_part[b]));
+                    CHK(dalloc(c, reinterpret_cast<void**>(&c->ez_part[b]), (size_t)nez * sizeof(double)));
+                }
+                c->ez_cap = nez;
+            }
+        }
     }
     return LISE_OK;
 }
@@ -406,7 +419,11 @@ template <typename T, int MODE>
 int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     a.j0 = j0;
     a.kcount = k;
-    if constexpr (std::is_same<T, float>::value) {
+    if constexpr (MODE == KP_ETAXY) {
+        // the forward-only eta pass exists for the register-FFT plane kernel only
+        if (!c->fast_xy) return fail(c, LISE_E_STATE, "forward-only eta pass without the register-FFT plane kernel");
+    }
+    if constexpr (std::is_same<T, float>::value && MODE != KP_ETAXY) {
         if (c->mfma_xy) {
             dim3 grid(c->lat.nz, (k + a.jg - 1) / a.jg);
             hipEvent_t ev;
@@ -437,18 +454,22 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
         prof_end(c, cls, ev);
         return check_launch(c, "kp_fast");
     }
-    dim3 grid(c->lat.nz / c->zb, (k + a.jg - 1) / a.jg);
-    // the kinetic-energy mode reuses LDS for a 256-double reduction
-    const size_t lds = std::max(kp_lds_bytes(c, c->zb), (size_t)kThreads * sizeof(double));
-    hipEvent_t ev;
-    prof_begin(c, cls, &ev);
-    if (c->ppt == 4) {
-        hipLaunchKernelGGL((kp_kernel<T, MODE, 4>), grid, dim3(kThreads), lds, c->stream, a);
+    if constexpr (MODE == KP_ETAXY) {
+        return LISE_E_STATE;   // not reached (checked above)
     } else {
-        hipLaunchKernelGGL((kp_kernel<T, MODE, 16>), grid, dim3(kThreads), lds, c->stream, a);
+        dim3 grid(c->lat.nz / c->zb, (k + a.jg - 1) / a.jg);
+        // the kinetic-energy mode reuses LDS for a 256-double reduction
+        const size_t lds = std::max(kp_lds_bytes(c, c->zb), (size_t)kThreads * sizeof(double));
+        hipEvent_t ev;
+        prof_begin(c, cls, &ev);
+        if (c->ppt == 4) {
+            hipLaunchKernelGGL((kp_kernel<T, MODE, 4>), grid, dim3(kThreads), lds, c->stream, a);
+        } else {
+            hipLaunchKernelGGL((kp_kernel<T, MODE, 16>), grid, dim3(kThreads), lds, c->stream, a);
+        }
+        prof_end(c, cls, ev);
+        return check_launch(c, "kp_kernel");
     }
-    prof_end(c, cls, ev);
-    return check_launch(c, "kp_kernel");
 }
 
 template <typename T, int NZ>
@@ -463,7 +484,8 @@ void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st) {
 }
 
 template <typename T>
-int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, hipStream_t st) {
+int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, hipStream_t st,
+                double* ezpart = nullptr) {
     if (c->fast_z) {
         KZFastArgs<T> f;
         f.nxy = (long long)c->lat.nx * c->lat.ny;
@@ -476,6 +498,8 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
         f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
         f.in = in;
         f.G = reinterpret_cast<cpx<T>*>(Gdst);
+        f.ezpart = ezpart;
+        f.nu = c->C == 2 ? 1 : 2;
         hipEvent_t ev;
         prof_begin(c, 1, &ev, st);
         switch (c->lat.nz) {
@@ -521,8 +545,16 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
 // z-scratch buffers alternate and events order every reuse.
 // eta_j = <x_j | H | x_j> (Eq. sp_en) for the qpwfs [j0, j0 + k) of the vector
 // x = main.in with the fields of `main`; needs the chunk's z-term in main.G.
+//
+// With the register-FFT kernels on both axes (cheap path) the z kernel of the
+// chunk has already written sum_z Re(x^* T_z x) per column into ez (Parseval
+// on its forward transform), and the plane pass only needs a forward xy
+// transform of x (Parseval again) and the local terms: it reads x alone, not
+// the z-term.  Otherwise the plane kernel recomputes H x in full (mode KP_ETA).
+bool eta_cheap(const lise_ctx* c) { return c->fast_xy && c->fast_z; }
+
 template <typename T>
-int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k) {
+int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k, const double* ez) {
     KPArgs<T> e = main;
     e.jg = 1;
     e.eta = nullptr;
@@ -530,9 +562,16 @@ int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k) {
     e.out = e.acc = e.deriv = nullptr;
     e.a1 = e.a2 = e.a3 = e.a4 = e.a5 = e.a6 = nullptr;
     e.epart = c->eta_part;
-    CHK((launch_kp_t<T, KP_ETA>(c, e, j0, k, 3)));
     const int nblk = c->lat.nz / c->zb;
     const double a3 = c->lat.a * c->lat.a * c->lat.a;
+    if (ez) {
+        CHK((launch_kp_t<T, KP_ETAXY>(c, e, j0, k, 3)));
+        const long long nez = (long long)c->C * c->lat.nx * c->lat.ny * kz_lanes_of(c->lat.nz);
+        hipLaunchKernelGGL(eta_reduce2_kernel, dim3((unsigned)k), dim3(256), 0, c->stream, c->eta_part, nblk, ez, nez,
+                           a3, c->eta + j0);
+        return check_launch(c, "eta_reduce2_kernel");
+    }
+    CHK((launch_kp_t<T, KP_ETA>(c, e, j0, k, 3)));
     hipLaunchKernelGGL(eta_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, c->stream, c->eta_part,
                        nblk, k, a3, c->eta + j0);
     return check_launch(c, "eta_reduce_kernel");
@@ -551,23 +590,25 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
         HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
         HIPCHK(c, hipStreamWaitEvent(c->s2, c->ev_start, 0));
     }
+    const bool cheap = eta_op == 1 && eta_cheap(c);
     for (long long j0 = first, ci = 0; j0 < first + count; j0 += c->chunk, ++ci) {
         const int k = (int)std::min<long long>(c->chunk, first + count - j0);
         const int b = ov ? (int)(ci & 1) : 0;
         void* Gb = c->Gbuf[b];
+        double* ez = cheap ? c->ez_part[b] : nullptr;
         if (!c->fused) {
             if (ov) {
                 if (ci >= 2) HIPCHK(c, hipStreamWaitEvent(c->s2, c->ev_kp[b], 0));
-                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->s2));
+                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->s2, ez));
                 HIPCHK(c, hipEventRecord(c->ev_kz[b], c->s2));
                 HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_kz[b], 0));
             } else {
-                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->stream));
+                CHK(launch_kz_t<T>(c, a.in, j0, k, Gb, c->stream, ez));
             }
         }
         a.G = reinterpret_cast<const cpx<T>*>(Gb);
         a.accumulate = (dens && ci > 0) ? 1 : 0;
-        if (eta_op == 1) CHK(eta_pass_t<T>(c, a, j0, k));
+        if (eta_op == 1) CHK(eta_pass_t<T>(c, a, j0, k, ez));
         CHK((launch_kp_t<T, MODE>(c, a, j0, k, cls)));
         if (ov) HIPCHK(c, hipEventRecord(c->ev_kp[b], c->stream));
     }
@@ -1818,6 +1859,7 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->eta));
     dfree(reinterpret_cast<void**>(&c->eta_part));
+    for (int b = 0; b < 2; ++b) dfree(reinterpret_cast<void**>(&c->ez_part[b]));
     dfree(reinterpret_cast<void**>(&c->bad));
     dfree(reinterpret_cast<void**>(&c->dtime));
     dfree(reinterpret_cast<void**>(&c->dkin));

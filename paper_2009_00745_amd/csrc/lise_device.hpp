@@ -229,7 +229,7 @@ __device__ __forceinline__ int signed_mode(int i, int n) { return (2 * i < n) ? 
 // ---------------------------------------------------------------------------
 // Kernel arguments
 
-enum KpMode { KP_APPLY = 0, KP_ABM1 = 1, KP_ABM2 = 2, KP_KINETIC = 3, KP_ETA = 4 };
+enum KpMode { KP_APPLY = 0, KP_ABM1 = 1, KP_ABM2 = 2, KP_KINETIC = 3, KP_ETA = 4, KP_ETAXY = 5 };
 
 template <typename T>
 struct KPArgs {
@@ -540,6 +540,26 @@ __global__ void __launch_bounds__(256) eta_reduce_kernel(const double* __restric
     double s = 0.0;
     for (int b = 0; b < nblk; ++b) s += part[(long long)j * nblk + b];
     eta[j] = a3 * s;
+}
+
+// eta_j = a^3 (sum of the nblk plane partials + sum of the nez z-kinetic
+// partials of qpwf j), one workgroup per qpwf, fixed-order sums (strided per
+// thread, then a tree): the cheap eta pass of the register-FFT kernels.
+__global__ void __launch_bounds__(256) eta_reduce2_kernel(const double* __restrict__ part, int nblk,
+                                                          const double* __restrict__ ezpart, long long nez,
+                                                          double a3, double* __restrict__ eta) {
+    __shared__ double red[256];
+    const int j = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (long long i = t; i < nez; i += 256) s += ezpart[(long long)j * nez + i];
+    for (int b = t; b < nblk; b += 256) s += part[(long long)j * nblk + b];
+    red[t] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
+        __syncthreads();
+    }
+    if (t == 0) eta[j] = a3 * red[0];
 }
 
 // ---------------------------------------------------------------------------

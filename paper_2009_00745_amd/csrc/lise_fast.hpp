@@ -237,6 +237,10 @@ struct KZFastArgs {
     const cpx<T>* tw;    // W_nz^j, j < nz
     const cpx<T>* in;
     cpx<T>* G;
+    // optional: per thread, +-sum_z Re(x^* T_z x) = +-sum_k cz m^2 |X_k|^2
+    // (Parseval; + for the u components c < nu, - for v), for the eta pass
+    double* ezpart;
+    int nu;
 };
 
 template <typename T, int NZ>
@@ -253,11 +257,15 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
 #pragma unroll
     for (int z = 0; z < NZ; ++z) x[z] = src[z * a.nxy];
     RegFft<T, NZ, 1, false>::run(x, tab);
+    double e = 0.0;
 #pragma unroll
     for (int z = 0; z < NZ; ++z) {
         const int m = (2 * z < NZ) ? z : z - NZ;
-        x[z] = (a.cz * T(m * m)) * x[z];
+        const T f = a.cz * T(m * m);
+        if (a.ezpart) e += double(f) * (double(x[z].re) * double(x[z].re) + double(x[z].im) * double(x[z].im));
+        x[z] = f * x[z];
     }
+    if (a.ezpart) a.ezpart[col] = (int)(jc % a.C) < a.nu ? e : -e;
     RegFft<T, NZ, 1, true>::run(x, tab);
 #pragma unroll
     for (int z = 0; z < NZ; ++z) dst[z * a.nxy] = x[z];
@@ -271,9 +279,13 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
 #define LISE_KZ_LANES 1
 #endif
 
+__host__ __device__ constexpr int kz_lanes_of(int nz) {
+    return (LISE_KZ_LANES > 1 && nz % LISE_KZ_LANES == 0 && nz / LISE_KZ_LANES >= 2) ? LISE_KZ_LANES : 1;
+}
+
 template <int NZ>
 constexpr int kz_lanes() {
-    return (LISE_KZ_LANES > 1 && NZ % LISE_KZ_LANES == 0 && NZ / LISE_KZ_LANES >= 2) ? LISE_KZ_LANES : 1;
+    return kz_lanes_of(NZ);
 }
 
 template <typename T, int NZ, int L>
@@ -296,12 +308,16 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     for (int q = 0; q < P; ++q) x[q] = src[(s + L * q) * a.nxy];
     lane_fwd<T, P, L>(x, tab, s);
     const int brs = bitrev(s, L);
+    double e = 0.0;
 #pragma unroll
     for (int k1 = 0; k1 < P; ++k1) {
         const int kz = k1 + P * brs;
         const int m = (2 * kz < NZ) ? kz : kz - NZ;
-        x[k1] = (a.cz * T(m * m)) * x[k1];
+        const T f = a.cz * T(m * m);
+        if (a.ezpart) e += double(f) * (double(x[k1].re) * double(x[k1].re) + double(x[k1].im) * double(x[k1].im));
+        x[k1] = f * x[k1];
     }
+    if (a.ezpart) a.ezpart[t] = (int)(jc % a.C) < a.nu ? e : -e;
     lane_inv<T, P, L>(x, tab, s);
 #pragma unroll
     for (int q = 0; q < P; ++q) dst[(s + L * q) * a.nxy] = x[q];
@@ -389,18 +405,44 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                     const int ky = k1 + P * brs;
                     const int my = (2 * ky < N) ? ky : ky - N;
                     const T f = fx + a.cy * T(my * my);
-                    xa[k1] = f * xa[k1];
-                    xb[k1] = f * xb[k1];
+                    if constexpr (MODE == KP_ETAXY) {
+                        // Parseval: sum_r f^* T_xy f = sum_k (k^2/2 / nxy) |F|^2; H has -T on v
+                        ekin += double(f) * (double(xa[k1].re) * double(xa[k1].re) + double(xa[k1].im) * double(xa[k1].im) -
+                                             double(xb[k1].re) * double(xb[k1].re) - double(xb[k1].im) * double(xb[k1].im));
+                    } else {
+                        xa[k1] = f * xa[k1];
+                        xb[k1] = f * xb[k1];
+                    }
                 }
-                lane_inv<T, P, L>(xa, tab, s);
-                lane_inv<T, P, L>(xb, tab, s);
+                if constexpr (MODE != KP_ETAXY) {
+                    lane_inv<T, P, L>(xa, tab, s);
+                    lane_inv<T, P, L>(xb, tab, s);
 #pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    La[col * LD + s + L * q] = xa[q];
-                    Lb[col * LD + s + L * q] = xb[q];
+                    for (int q = 0; q < P; ++q) {
+                        La[col * LD + s + L * q] = xa[q];
+                        Lb[col * LD + s + L * q] = xb[q];
+                    }
                 }
             }
             __syncthreads();
+            if constexpr (MODE == KP_ETAXY) {
+                // the local part of <f|H f> from the point values: (V - mu_a)|u|^2
+                // - (V - mu_b)|v|^2 + 2 s Re(Delta u^* v)
+                if (act) {
+                    const T sg = T(a.sgn[pr]);
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        const long long rpt = (long long)z * nxy + row * N + s + L * q;
+                        const double V = a.V[rpt];
+                        const double Dr = double(sg) * a.D[2 * rpt], Di = double(sg) * a.D[2 * rpt + 1];
+                        const double ur = double(fa[q].re), ui = double(fa[q].im);
+                        const double vr = double(fb[q].re), vi = double(fb[q].im);
+                        ekin += (V - a.mu_a[pr]) * (ur * ur + ui * ui) - (V - a.mu_b[pr]) * (vr * vr + vi * vi) +
+                                2.0 * (Dr * (ur * vr + ui * vi) - Di * (ur * vi - ui * vr));
+                    }
+                }
+                continue;   // the next pair reuses La, Lb only after the barrier above
+            }
             if (act) {
 #pragma unroll
                 for (int k1 = 0; k1 < P; ++k1) {
@@ -423,7 +465,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             __syncthreads();
         }
     }
-    if (MODE == KP_KINETIC || MODE == KP_ETA) {
+    if (MODE == KP_KINETIC || MODE == KP_ETA || MODE == KP_ETAXY) {
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = ekin;
         __syncthreads();

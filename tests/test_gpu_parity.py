@@ -188,6 +188,25 @@ def test_phase_removal_step(lise):
         assert max(e) < tol
 
 
+def test_phase_removal_two_eta_passes_agree(lise):
+    """The Parseval eta pass of the register-FFT kernels and the full recomputation of
+    the generic kernels give the same evolution to rounding (FP64, 16^3 and 20^3)."""
+    for w in (wl.config2(M=12, n=16), wl.config3(M=8, n=20, precision=wl.FP64)):
+        w.functional.remove_phase = 1
+        outs = []
+        for generic in (0, 1):
+            say(f"{w.name} phase removed, generic kernels = {generic}, 8 steps")
+            ctx = lise.Context(w.lattice, w.M, w.functional)
+            ctx.set_tuning(generic=generic)
+            ctx.set_qpwf(0, w.qpwfs())
+            ctx.step(w.dt, 8)
+            outs.append(ctx.get_qpwf(0, w.M))
+            ctx.close()
+        e = rel_l2(outs[0], outs[1])
+        say(f"  rel L2 between the two eta passes {e:.3e}")
+        assert e < 1e-12
+
+
 def test_phase_removal_frozen_eigenvectors_stay_put(lise):
     """Frozen fields, plane-wave BdG eigenvectors: with the phase removed y' = 0."""
     lat = wl.Lattice(16, 16, 16, 1.0)
