@@ -366,7 +366,7 @@ def main():
                 "n": float(np.linalg.norm(n_p - n64) / np.linalg.norm(n64)),
                 "kappa": float(np.linalg.norm(k_p - k64) / np.linalg.norm(k64))} if same else None,
             "after_steps": int(sp), "tuning": chosenp,
-            "note": "eta pass re-reads x and the z-term: 24 state arrays per step instead of 20"}
+            "note": "eta by Parseval on the register-FFT path: the pass re-reads x once, 22 state arrays per step instead of 20"}
 
     if args.batched and args.workload == "cfg2":
         variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
