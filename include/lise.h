@@ -144,8 +144,10 @@ typedef struct {
  *                scratch buffer and keeps it cache-resident)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
  *                (sets the number of density partial sums)
- *   fused      : 0 or 1 = whole-cube kernel when the cube fits in LDS,
- *                -1 = never (always the z-axis kernel plus plane kernel)
+ *   fused      : whole-cube kernel (one pass, the cube in LDS): 1 = whenever
+ *                the cube fits in LDS; 0 = only where the register-FFT
+ *                kernels below do not cover the lattice; -1 = never (always
+ *                the z-axis kernel plus the plane kernel)
  *   generic    : 1 = use the runtime-sized LDS FFT kernels even where a
  *                size-specialised register-FFT kernel exists (sides 8, 16,
  *                20, 24, 32, 48, 64; square xy-planes for the plane kernel)

@@ -83,7 +83,7 @@ struct lise_ctx {
     AxisPlan px, py, pz;
 
     // tuning
-    int chunk = 0, jg = 16, fused_pref = 1, generic = 0;
+    int chunk = 0, jg = 16, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
     bool fast_xy = false, fast_z = false;   // size-specialised register-FFT kernels
@@ -200,7 +200,19 @@ bool fast_side(int n) {
 
 size_t fast_kp_lds(const lise_ctx* c) {
     const size_t n = c->lat.nx;
-    return (n + 2 * n * (n + 1)) * c->esz;
+    const size_t zp = plane_zp_of((int)c->esz / 2, (int)n);
+    return (n + zp * 2 * n * (n + 1)) * c->esz;
+}
+
+// workgroups along z of one plane-kernel launch (= partial sums per qpwf of
+// the reducing modes)
+int plane_grid_x(const lise_ctx* c) {
+    if (c->fast_xy) {
+        const int zp = plane_zp_of((int)c->esz / 2, c->lat.nx);
+        return (c->lat.nz + zp - 1) / zp;
+    }
+    if (c->mfma_xy) return c->lat.nz;
+    return c->lat.nz / c->zb;
 }
 
 // Allow every kernel that takes dynamic LDS to use the device's whole LDS,
@@ -261,7 +273,12 @@ int configure(lise_ctx* c) {
     const long long nxy = (long long)nx * ny;
     // fused: the whole cube of one component pair in LDS (two buffers)
     c->fused = false;
-    if (c->fused_pref && !c->mfma_mode && kp_lds_bytes(c, nz) <= c->lds_limit && c->N <= 16LL * kThreads)
+    // auto: the whole-cube LDS kernel only where the register-FFT kernels do
+    // not cover the lattice (they measured faster where both exist)
+    const bool reg_fft = !c->generic && nx == ny && fast_side(nx) && fast_side(nz) && fast_kp_lds(c) <= c->lds_limit &&
+                         c->tw_full_xy >= 0 && c->tw_full_z >= 0;
+    const bool want_fused = c->fused_mode > 0 || (c->fused_mode == 0 && !reg_fft);
+    if (want_fused && !c->mfma_mode && kp_lds_bytes(c, nz) <= c->lds_limit && c->N <= 16LL * kThreads)
         c->fused = true;
     if (c->fused) {
         c->zb = nz;
@@ -439,7 +456,7 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
         }
     }
     if (c->fast_xy) {
-        dim3 grid(c->lat.nz, (k + a.jg - 1) / a.jg);
+        dim3 grid((unsigned)plane_grid_x(c), (k + a.jg - 1) / a.jg);
         hipEvent_t ev;
         prof_begin(c, cls, &ev);
         switch (c->lat.nx) {
@@ -562,7 +579,7 @@ int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k, const do
     e.out = e.acc = e.deriv = nullptr;
     e.a1 = e.a2 = e.a3 = e.a4 = e.a5 = e.a6 = nullptr;
     e.epart = c->eta_part;
-    const int nblk = c->lat.nz / c->zb;
+    const int nblk = plane_grid_x(c);
     const double a3 = c->lat.a * c->lat.a * c->lat.a;
     if (ez) {
         CHK((launch_kp_t<T, KP_ETAXY>(c, e, j0, k, 3)));
@@ -934,7 +951,7 @@ int kinetic_energy_t(lise_ctx* c, double* ekin) {
     a.D = c->D_cur;
     a.in = ycur<T>(c);
     a.G = reinterpret_cast<const cpx<T>*>(c->G);
-    const long long nwg_per = (long long)(c->lat.nz / c->zb) * ((c->chunk + c->jg - 1) / c->jg);  // zb = 1 on the fast path
+    const long long nwg_per = (long long)plane_grid_x(c) * ((c->chunk + c->jg - 1) / c->jg);
     if (c->red_cap < nwg_per) {
         dfree(reinterpret_cast<void**>(&c->red));
         CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)std::max<long long>(nwg_per, 4096) * sizeof(double)));
@@ -948,7 +965,7 @@ int kinetic_energy_t(lise_ctx* c, double* ekin) {
         if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k, c->Gbuf[0], c->stream));
         a.G = reinterpret_cast<const cpx<T>*>(c->Gbuf[0]);
         CHK((launch_kp_t<T, KP_KINETIC>(c, a, j0, k, 3)));
-        const long long nwg = (long long)(c->lat.nz / c->zb) * ((k + c->jg - 1) / c->jg);
+        const long long nwg = (long long)plane_grid_x(c) * ((k + c->jg - 1) / c->jg);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->red, nwg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (long long i = 0; i < nwg; ++i) sum += h[i];
@@ -1477,7 +1494,7 @@ int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     if (c->s2) HIPCHK(c, hipStreamSynchronize(c->s2));
     c->chunk = t->chunk_qpwf;
     if (t->jgroup > 0) c->jg = t->jgroup;
-    c->fused_pref = (t->fused < 0) ? 0 : 1;
+    c->fused_mode = t->fused < 0 ? -1 : (t->fused > 0 ? 1 : 0);
     c->generic = t->generic ? 1 : 0;
     c->overlap = t->no_overlap ? 0 : 1;
     c->use_graph = t->graph ? 1 : 0;
@@ -1760,7 +1777,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
                 lise_tuning t{};
                 t.chunk_qpwf = (int32_t)ch;
                 t.jgroup = jg;
-                t.fused = c->fused_pref ? 0 : -1;
+                t.fused = c->fused_mode;
                 t.generic = c->generic;
                 t.no_overlap = nov;
                 t.graph = c->use_graph;

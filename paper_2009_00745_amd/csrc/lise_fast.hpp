@@ -210,17 +210,36 @@ __device__ __forceinline__ void lane_inv(cpx<T>* x, const cpx<T>* __restrict__ t
 #define LISE_PLANE_MAXP_F32 2
 #endif
 
-template <typename T, int N>
-constexpr int plane_lanes() {
-    constexpr int maxp = sizeof(T) == 8 ? LISE_PLANE_MAXP_F64 : LISE_PLANE_MAXP_F32;
+// esz: bytes of the real type (8 = float64, 4 = float32)
+__host__ __device__ constexpr int plane_lanes_of(int esz, int N) {
+    const int maxp = esz == 8 ? LISE_PLANE_MAXP_F64 : LISE_PLANE_MAXP_F32;
     int L = 4;
     while (N / L > maxp && L < 16 && N % (2 * L) == 0) L *= 2;
     return L;
 }
 
+// xy-planes per workgroup: where a plane's L*N lanes leave a wave partly
+// idle (N = 8: 32 lanes, N = 20: 80), a workgroup takes 2 or 4 planes
+__host__ __device__ constexpr int plane_zp_of(int esz, int N) {
+    const int t = plane_lanes_of(esz, N) * N;
+    for (int zp = 1; zp <= 4; zp *= 2)
+        if ((zp * t) % 64 == 0 && zp * t <= 1024) return zp;
+    return 1;
+}
+
+template <typename T, int N>
+constexpr int plane_lanes() {
+    return plane_lanes_of((int)sizeof(T), N);
+}
+
+template <typename T, int N>
+constexpr int plane_zp() {
+    return plane_zp_of((int)sizeof(T), N);
+}
+
 template <typename T, int N>
 constexpr int plane_block() {
-    constexpr int t = plane_lanes<T, N>() * N;
+    constexpr int t = plane_zp<T, N>() * plane_lanes<T, N>() * N;
     return (t + 63) / 64 * 64;
 }
 
@@ -329,7 +348,7 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
 
 template <typename T, int N>
 constexpr size_t kp_fast_lds() {
-    return (size_t)(N + 2 * N * (N + 1)) * sizeof(cpx<T>);
+    return (size_t)(N + plane_zp<T, N>() * 2 * N * (N + 1)) * sizeof(cpx<T>);
 }
 
 #ifndef LISE_KP_MIN_WAVES
@@ -341,18 +360,22 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     constexpr int L = plane_lanes<T, N>();
     constexpr int P = N / L;
     constexpr int LD = N + 1;
+    constexpr int ZP = plane_zp<T, N>();
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* La = tab + N;
-    cpx<T>* Lb = La + N * LD;
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
     for (int i = tid; i < N; i += nth) tab[i] = twN[i];
-    const bool act = tid < L * N;
-    const int row = tid / L;
-    const int s = tid % L;
+    // plane zi of the workgroup's ZP planes; its lines over L lanes
+    const int zi = tid / (L * N);
+    const int tl = tid - zi * (L * N);
+    const int z = blockIdx.x * ZP + zi;
+    const bool act = zi < ZP && z < a.nz;
+    cpx<T>* La = tab + N + (act ? zi : 0) * 2 * N * LD;
+    cpx<T>* Lb = La + N * LD;
+    const int row = tl / L;
+    const int s = tl % L;
     const int brs = bitrev(s, L);
-    const int z = blockIdx.x;
     constexpr long long nxy = (long long)N * N;
     const long long N3 = nxy * a.nz;
     const int jbeg = blockIdx.y * a.jg;

@@ -48,6 +48,7 @@ APPLY_CASES = [
     # (nx, ny, nz, a, C, M, precision, tuning)
     (4, 4, 4, 1.0, 2, 5, 0, {}),
     (8, 8, 8, 1.0, 2, 7, 0, {}),
+    (8, 8, 8, 1.0, 2, 7, 0, {"fused": 1}),
     (8, 8, 8, 1.0, 2, 7, 0, {"fused": -1}),
     (6, 10, 8, 0.8, 2, 4, 0, {}),
     (6, 10, 8, 0.8, 2, 9, 0, {"fused": -1, "chunk_qpwf": 4, "jgroup": 3}),
@@ -60,6 +61,7 @@ APPLY_CASES = [
     (24, 24, 24, 1.0, 4, 2, 0, {}),
     (20, 20, 16, 1.0, 2, 3, 0, {"chunk_qpwf": 2, "jgroup": 1}),
     (16, 16, 16, 1.0, 2, 6, 1, {}),
+    (16, 16, 16, 1.0, 2, 6, 1, {"fused": 1}),
     (16, 16, 16, 1.0, 2, 6, 1, {"fused": -1}),
     (48, 48, 48, 1.0, 2, 2, 1, {}),
     (48, 48, 48, 1.0, 2, 2, 1, {"generic": 1}),
