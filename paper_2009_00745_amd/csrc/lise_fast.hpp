@@ -368,12 +368,17 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
     for (int i = tid; i < N; i += nth) tab[i] = twN[i];
-    // plane zi of the workgroup's ZP planes; its lines over L lanes
-    const int zi = tid / (L * N);
-    const int tl = tid - zi * (L * N);
-    const int z = blockIdx.x * ZP + zi;
-    const bool act = zi < ZP && z < a.nz;
-    cpx<T>* La = tab + N + (act ? zi : 0) * 2 * N * LD;
+    // plane zi of the workgroup's ZP planes; its lines over L lanes (with one
+    // plane per workgroup the index arithmetic reduces to the plain form)
+    int zi = 0, tl = tid, z = blockIdx.x;
+    bool act = tid < L * N;
+    if constexpr (ZP > 1) {
+        zi = tid / (L * N);
+        tl = tid - zi * (L * N);
+        z = blockIdx.x * ZP + zi;
+        act = zi < ZP && z < a.nz;
+    }
+    cpx<T>* La = tab + N + (ZP > 1 && act ? zi : 0) * 2 * N * LD;
     cpx<T>* Lb = La + N * LD;
     const int row = tl / L;
     const int s = tl % L;
