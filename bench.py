@@ -101,7 +101,7 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     chosen = None
     if autotune:
         t0 = time.time()
-        chosen = ctx.autotune(w.dt, 2)
+        chosen = ctx.autotune(w.dt, 3)
         log(f"{w.name}: autotune picked {chosen} in {time.time() - t0:.1f}s")
     if warmup:
         ctx.step(w.dt, warmup)

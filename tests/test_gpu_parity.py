@@ -140,6 +140,20 @@ def test_config1_full_100_steps(lise):
     assert np.allclose(obs["r_cm"], o["r_cm"], atol=1e-10)
 
 
+def test_long_run_fp64_stays_on_the_oracle(lise):
+    """500 ABM steps (8^3, M = 64, config-1 recipe, then again with phase removal):
+    the FP64 path stays on the oracle's trajectory to round-off accumulation."""
+    for rp in (0, 1):
+        w = wl.config1(M=64)
+        w.functional.remove_phase = rp
+        say(f"long run {w.name} remove_phase={rp}: 500 steps")
+        got, n, k, t, s, obs, ev = run_pair(lise, w, 500)
+        n0, k0 = oracle.densities(ev.y, w.functional)
+        e = (rel_l2(got, ev.y), rel_l2(n, n0), rel_l2(k, k0))
+        say(f"  rel L2 after 500 steps: {e}")
+        assert s == 503 and max(e) < 1e-11
+
+
 def test_config2_reduced_with_bump(lise):
     """32^3 lowest-|k| BCS + ramped Gaussian well, M = 32, 12 ABM steps."""
     w = wl.config2(M=32)
