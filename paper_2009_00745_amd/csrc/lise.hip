@@ -1766,7 +1766,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
         (void)hipEventElapsedTime(ms, e0, e1);
         return r;
     };
-    // round 1: every candidate; round 2: the three fastest again over twice the
+    // first pass: every candidate; second pass: the three fastest again over twice the
     // steps, so that timing noise between close candidates does not decide
     std::vector<std::pair<float, lise_tuning>> timed;
     int rc = LISE_OK;
