@@ -143,7 +143,7 @@ typedef struct {
  *   chunk_qpwf : qpwfs per launch of the two apply-H kernels (bounds the
  *                scratch buffer and keeps it cache-resident)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
- *                (sets the number of density partial sums)
+ *                (sets the number of density partial sums; default 32)
  *   fused      : whole-cube kernel (one pass, the cube in LDS): 1 = whenever
  *                the cube fits in LDS; 0 = only where the register-FFT
  *                kernels below do not cover the lattice; -1 = never (always
@@ -237,7 +237,7 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
 int lise_profile(lise_ctx *c, int32_t enable);
 int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 
-/* Timed search over launch tuning (chunk size, qpwfs per plane workgroup,
+/* Timed search over launch tuning (chunk size, qpwfs per plane workgroup 8/16/32/64,
  * z-kernel overlap) for this system: each candidate runs one untimed and
  * `trial_steps` timed ABM steps with step size dt on the live state (the
  * state advances; results change only in rounding); the three fastest run

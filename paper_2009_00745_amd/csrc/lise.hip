@@ -83,7 +83,7 @@ struct lise_ctx {
     AxisPlan px, py, pz;
 
     // tuning
-    int chunk = 0, jg = 16, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
+    int chunk = 0, jg = 32, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
     bool fast_xy = false, fast_z = false;   // size-specialised register-FFT kernels
@@ -1749,7 +1749,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
                                      std::min<long long>(c->M, std::max<long long>(16, gib / 4))};
     std::sort(chunks.begin(), chunks.end());
     chunks.erase(std::unique(chunks.begin(), chunks.end()), chunks.end());
-    const int jgs[] = {8, 16, 32};
+    const int jgs[] = {8, 16, 32, 64};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
