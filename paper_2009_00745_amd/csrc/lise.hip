@@ -84,6 +84,7 @@ struct lise_ctx {
 
     // tuning
     int chunk = 0, jg = 32, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
+    bool stream_hint = false;   // z kernel takes nontemporal hints (as the plane kernel does)
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
     bool fast_xy = false, fast_z = false;   // size-specialised register-FFT kernels
@@ -298,6 +299,7 @@ int configure(lise_ctx* c) {
                  fast_kp_lds(c) <= c->lds_limit && c->tw_full_xy >= 0;
     c->fast_z = !c->fused && !c->generic && fast_side(nz) && c->tw_full_z >= 0;
     if (c->fast_xy || c->mfma_xy) c->zb = 1;
+    c->stream_hint = c->mfma_xy || (c->fast_xy && plane_stream_hint_of(c->esz / 2, nx));
     // the generic LDS kernels must fit where they are the ones that run
     if (!c->fused && !c->fast_xy && !c->mfma_xy && kp_lds_bytes(c, c->zb) > c->lds_limit)
         return fail(c, LISE_E_UNSUPPORTED, "xy-plane %dx%d does not fit in LDS (%zu > %zu bytes)", nx, ny,
@@ -489,15 +491,26 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
     }
 }
 
-template <typename T, int NZ>
-void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st) {
+// nt: nontemporal hints on the column loads and scratch stores, taken where
+// the plane kernel of the lattice takes them (whole-line plane rows; small
+// lattices keep the default cache policy throughout)
+template <typename T, int NZ, bool NT>
+void launch_kz_fast_nt(const KZFastArgs<T>& f, hipStream_t st) {
     constexpr int L = kz_lanes<NZ>();
     const long long threads = f.ncols * L;
     dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
     if constexpr (L > 1)
-        hipLaunchKernelGGL((kz_lanes_kernel<T, NZ, L>), grid, dim3(kThreads), 0, st, f);
+        hipLaunchKernelGGL((kz_lanes_kernel<T, NZ, L, NT>), grid, dim3(kThreads), 0, st, f);
     else
-        hipLaunchKernelGGL((kz_fast<T, NZ>), grid, dim3(kThreads), 0, st, f);
+        hipLaunchKernelGGL((kz_fast<T, NZ, NT>), grid, dim3(kThreads), 0, st, f);
+}
+
+template <typename T, int NZ>
+void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st, bool nt) {
+    if (nt)
+        launch_kz_fast_nt<T, NZ, true>(f, st);
+    else
+        launch_kz_fast_nt<T, NZ, false>(f, st);
 }
 
 template <typename T>
@@ -520,13 +533,13 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
         hipEvent_t ev;
         prof_begin(c, 1, &ev, st);
         switch (c->lat.nz) {
-            case 8: launch_kz_fast_n<T, 8>(f, st); break;
-            case 16: launch_kz_fast_n<T, 16>(f, st); break;
-            case 20: launch_kz_fast_n<T, 20>(f, st); break;
-            case 24: launch_kz_fast_n<T, 24>(f, st); break;
-            case 32: launch_kz_fast_n<T, 32>(f, st); break;
-            case 48: launch_kz_fast_n<T, 48>(f, st); break;
-            default: launch_kz_fast_n<T, 64>(f, st); break;
+            case 8: launch_kz_fast_n<T, 8>(f, st, c->stream_hint); break;
+            case 16: launch_kz_fast_n<T, 16>(f, st, c->stream_hint); break;
+            case 20: launch_kz_fast_n<T, 20>(f, st, c->stream_hint); break;
+            case 24: launch_kz_fast_n<T, 24>(f, st, c->stream_hint); break;
+            case 32: launch_kz_fast_n<T, 32>(f, st, c->stream_hint); break;
+            case 48: launch_kz_fast_n<T, 48>(f, st, c->stream_hint); break;
+            default: launch_kz_fast_n<T, 64>(f, st, c->stream_hint); break;
         }
         prof_end(c, 1, ev, st);
         return check_launch(c, "kz_fast");

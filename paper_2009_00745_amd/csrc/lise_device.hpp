@@ -49,6 +49,51 @@ template <typename T>
 __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.re, s * a.im); }
 template <typename T>
 __device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return mk(a.re, -a.im); }
+// Loads and stores of the state arrays can carry the nontemporal hint (the
+// `nt` bit of global_load/global_store).  Where one instruction of a wave
+// covers whole 128-byte lines the hint raised bandwidth (a plain 1-read +
+// 1-write stream on gfx950: 5.4 -> 6.2 TB/s); where it covers parts of lines
+// (a 20-point plane row spread over 4 lanes) the next instruction fetched the
+// rest of the line again and the plane kernel ran up to 2.3x slower.  So each
+// kernel passes NT from its own access pattern.  Fields, twiddles and density
+// partials, which are reused, never take the hint.  LISE_STREAM_HINT=0 turns
+// the hint off everywhere.
+#ifndef LISE_STREAM_HINT
+#define LISE_STREAM_HINT 1
+#endif
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct vec2_of<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <typename T, bool NT>
+__device__ __forceinline__ cpx<T> ld_hint(const cpx<T>* p) {
+    if constexpr (NT && LISE_STREAM_HINT) {
+        typedef typename vec2_of<T>::type V;
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+        return mk(T(v.x), T(v.y));
+    } else {
+        return *p;
+    }
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void st_hint(cpx<T>* p, cpx<T> v) {
+    if constexpr (NT && LISE_STREAM_HINT) {
+        typedef typename vec2_of<T>::type V;
+        V w;
+        w.x = v.re;
+        w.y = v.im;
+        __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 // multiply by i * sigma, sigma = +1 or -1
 template <typename T, int SIG>
 __device__ __forceinline__ cpx<T> mul_isig(cpx<T> a) {
@@ -300,7 +345,7 @@ struct KPArgs {
 // phase removal on (a.eta set) the other modes apply H - eta_j (ej) instead
 // of H.
 
-template <typename T, int MODE, bool HASG>
+template <typename T, int MODE, bool HASG, bool NT>
 __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T> Ta, cpx<T> Tb, cpx<T> fa, cpx<T> fb,
                                                long long ea, long long eb, long long rpt, long long ga, long long gb,
                                                cpx<T> coef, T cdt, T ej,
@@ -309,8 +354,8 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
     // round trip to memory serves the z-term, the fields and the ABM history.
     cpx<T> Ga = mk(T(0), T(0)), Gb = mk(T(0), T(0));
     if constexpr (HASG) {
-        Ga = a.G[ga];
-        Gb = a.G[gb];
+        Ga = ld_hint<T, NT>(a.G + ga);
+        Gb = ld_hint<T, NT>(a.G + gb);
     }
     if constexpr (MODE == KP_KINETIC) {
         Tb = Tb + Gb;
@@ -321,14 +366,14 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
     const double Dre = a.D[2 * rpt], Dim = a.D[2 * rpt + 1];
     cpx<T> h1a, h1b, h2a, h2b, h3a, h3b, h4a, h4b, h5a, h5b;
     if constexpr (MODE == KP_ABM1) {
-        h1a = a.a1[ea]; h1b = a.a1[eb];
-        h2a = a.a2[ea]; h2b = a.a2[eb];
-        h3a = a.a3[ea]; h3b = a.a3[eb];
-        h4a = a.a4[ea]; h4b = a.a4[eb];
-        h5a = a.a5[ea]; h5b = a.a5[eb];
+        h1a = ld_hint<T, NT>(a.a1 + ea); h1b = ld_hint<T, NT>(a.a1 + eb);
+        h2a = ld_hint<T, NT>(a.a2 + ea); h2b = ld_hint<T, NT>(a.a2 + eb);
+        h3a = ld_hint<T, NT>(a.a3 + ea); h3b = ld_hint<T, NT>(a.a3 + eb);
+        h4a = ld_hint<T, NT>(a.a4 + ea); h4b = ld_hint<T, NT>(a.a4 + eb);
+        h5a = ld_hint<T, NT>(a.a5 + ea); h5b = ld_hint<T, NT>(a.a5 + eb);
     } else if constexpr (MODE == KP_ABM2) {
-        h1a = a.a1[ea]; h1b = a.a1[eb];
-        h5a = a.a5[ea]; h5b = a.a5[eb];
+        h1a = ld_hint<T, NT>(a.a1 + ea); h1b = ld_hint<T, NT>(a.a1 + eb);
+        h5a = ld_hint<T, NT>(a.a5 + ea); h5b = ld_hint<T, NT>(a.a5 + eb);
     }
     Ta = Ta + Ga;
     Tb = Tb + Gb;
@@ -378,22 +423,22 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
         const cpx<T> cb = sb + cdt * (T(51) * db + T(3) * h2b + h3b);
         va = (ca + Ya) - T(161.0 / 170.0) * h5a;   // m = p - 161/170 d_n
         vb = (cb + Yb) - T(161.0 / 170.0) * h5b;
-        a.a6[ea] = da;
-        a.a6[eb] = db;
-        a.a4[ea] = va;
-        a.a4[eb] = vb;
-        a.a1[ea] = Ya;
-        a.a1[eb] = Yb;
+        st_hint<T, NT>(a.a6 + ea, da);
+        st_hint<T, NT>(a.a6 + eb, db);
+        st_hint<T, NT>(a.a4 + ea, va);
+        st_hint<T, NT>(a.a4 + eb, vb);
+        st_hint<T, NT>(a.a1 + ea, Ya);
+        st_hint<T, NT>(a.a1 + eb, Yb);
     } else {   // KP_ABM2: in = m, a1 = Y -> y_{n+1}, a5 = d_n -> d_{n+1}
         const cpx<T> ma = mk(Ha.im, -Ha.re), mb = mk(Hb.im, -Hb.re);   // m' = -i H m
         const T k = T(17) * cdt;
         const cpx<T> ra = h1a - k * ma, rb = h1b - k * mb;             // d_{n+1}
         va = fa + T(161.0 / 170.0) * (h5a - ra);                        // y_{n+1}
         vb = fb + T(161.0 / 170.0) * (h5b - rb);
-        a.a1[ea] = va;
-        a.a1[eb] = vb;
-        a.a5[ea] = ra;
-        a.a5[eb] = rb;
+        st_hint<T, NT>(a.a1 + ea, va);
+        st_hint<T, NT>(a.a1 + eb, vb);
+        st_hint<T, NT>(a.a5 + ea, ra);
+        st_hint<T, NT>(a.a5 + eb, rb);
     }
     if (a.dens_src) {
         const double br = double(vb.re), bi = double(vb.im);
@@ -489,11 +534,11 @@ __global__ void __launch_bounds__(256) kp_kernel(const KPArgs<T> a) {
                 if (q >= P) continue;
                 const cpx<T> Ta = r[q], Tb = r[P + q];
                 if (a.fused)
-                    point_epilogue<T, MODE, false>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
+                    point_epilogue<T, MODE, false, false>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
                                                    (long long)z0 * nxy + q, 0, 0, coef, cdt, ej, dn[i], dkr[i],
                                                    dki[i], ekin);
                 else
-                    point_epilogue<T, MODE, true>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
+                    point_epilogue<T, MODE, true, false>(a, pr, Ta, Tb, fa[i], fb[i], offa + q, offb + q,
                                                   (long long)z0 * nxy + q, lofa + q, lofb + q, coef, cdt, ej, dn[i],
                                                   dkr[i], dki[i], ekin);
             }

@@ -239,6 +239,19 @@ constexpr int plane_zp() {
     return plane_zp_of((int)sizeof(T), N);
 }
 
+// nontemporal hints in the plane kernel: one load instruction of a wave reads
+// L consecutive points of each of its rows, so the hint is taken only where
+// those L points and a whole row are multiples of a 128-byte line (every
+// instruction then covers whole lines)
+__host__ __device__ constexpr bool plane_stream_hint_of(int esz, int N) {
+    return (plane_lanes_of(esz, N) * 2 * esz) % 128 == 0 && (N * 2 * esz) % 128 == 0;
+}
+
+template <typename T, int N>
+constexpr bool plane_stream_hint() {
+    return plane_stream_hint_of((int)sizeof(T), N);
+}
+
 template <typename T, int N>
 constexpr int plane_block() {
     constexpr int t = plane_zp<T, N>() * plane_lanes<T, N>() * N;
@@ -264,7 +277,7 @@ struct KZFastArgs {
     int nu;
 };
 
-template <typename T, int NZ>
+template <typename T, int NZ, bool NT>
 __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
     __shared__ cpx<T> tab[NZ];
     for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
@@ -276,7 +289,7 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
     cpx<T>* dst = a.G + jc * NZ * a.nxy + r;
     cpx<T> x[NZ];
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) x[z] = src[z * a.nxy];
+    for (int z = 0; z < NZ; ++z) x[z] = ld_hint<T, NT>(src + z * a.nxy);
     RegFft<T, NZ, 1, false>::run(x, tab);
     double e = 0.0;
 #pragma unroll
@@ -289,7 +302,7 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
     if (a.ezpart) a.ezpart[col] = (int)(jc % a.C) < a.nu ? e : -e;
     RegFft<T, NZ, 1, true>::run(x, tab);
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) dst[z * a.nxy] = x[z];
+    for (int z = 0; z < NZ; ++z) st_hint<T, NT>(dst + z * a.nxy, x[z]);
 }
 
 // z axis with a column split over L adjacent lanes (lane s holds z = s + L q,
@@ -309,7 +322,7 @@ constexpr int kz_lanes() {
     return kz_lanes_of(NZ);
 }
 
-template <typename T, int NZ, int L>
+template <typename T, int NZ, int L, bool NT>
 __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     constexpr int P = NZ / L;
     __shared__ cpx<T> tab[NZ];
@@ -326,7 +339,7 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     cpx<T>* dst = a.G + jc * NZ * a.nxy + r;
     cpx<T> x[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) x[q] = src[(s + L * q) * a.nxy];
+    for (int q = 0; q < P; ++q) x[q] = ld_hint<T, NT>(src + (s + L * q) * a.nxy);
     lane_fwd<T, P, L>(x, tab, s);
     const int brs = bitrev(s, L);
     double e = 0.0;
@@ -341,7 +354,7 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     if (a.ezpart) a.ezpart[t] = (int)(jc % a.C) < a.nu ? e : -e;
     lane_inv<T, P, L>(x, tab, s);
 #pragma unroll
-    for (int q = 0; q < P; ++q) dst[(s + L * q) * a.nxy] = x[q];
+    for (int q = 0; q < P; ++q) st_hint<T, NT>(dst + (s + L * q) * a.nxy, x[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,6 +374,7 @@ template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
     constexpr int L = plane_lanes<T, N>();
     constexpr int P = N / L;
+    constexpr bool NT = plane_stream_hint<T, N>();
     constexpr int LD = N + 1;
     constexpr int ZP = plane_zp<T, N>();
     extern __shared__ unsigned char smem_raw[];
@@ -405,8 +419,8 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             if (act) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    fa[q] = a.in[offa + row * N + s + L * q];
-                    fb[q] = a.in[offb + row * N + s + L * q];
+                    fa[q] = ld_hint<T, NT>(a.in + offa + row * N + s + L * q);
+                    fb[q] = ld_hint<T, NT>(a.in + offb + row * N + s + L * q);
                     xa[q] = fa[q];
                     xb[q] = fb[q];
                 }
@@ -488,7 +502,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                     const int pt = row * N + s + L * q;
                     // the plane kernels never run fused: the z-term is always in G
                     const long long ea = offa + pt, eb = offb + pt;
-                    point_epilogue<T, MODE, true>(a, pr, xa[q], xb[q], fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
+                    point_epilogue<T, MODE, true, NT>(a, pr, xa[q], xb[q], fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
                                                   lofa + pt, lofb + pt, coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
                 }
             }

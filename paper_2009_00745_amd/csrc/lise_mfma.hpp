@@ -100,8 +100,8 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
             for (int e = tid; e < N * N; e += nth) {
                 const int y = e / N, x = e - y * N;
-                Fa[y * LD + x] = a.in[offa + e];
-                Fb[y * LD + x] = a.in[offb + e];
+                Fa[y * LD + x] = ld_hint<float, true>(a.in + offa + e);
+                Fb[y * LD + x] = ld_hint<float, true>(a.in + offb + e);
             }
             __syncthreads();
             f32x4 ar[TPW], ai[TPW], br[TPW], bi[TPW];
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__((mfma_block<N>())) kp_mfma(const KPArgs<float>
                     const int y = 16 * ty + lk + r, x = 16 * (tx0 + u) + li;
                     const int pt = y * N + x;
                     const cpx<float> Ta = mk(ar[u][r], ai[u][r]), Tb = mk(br[u][r], bi[u][r]);
-                    point_epilogue<float, MODE, true>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt,
+                    point_epilogue<float, MODE, true, true>(a, pr, Ta, Tb, Fa[y * LD + x], Fb[y * LD + x], offa + pt,
                                                       offb + pt, (long long)z * nxy + pt, lofa + pt, lofb + pt, coef,
                                                       cdt, ej, dn[u * 4 + r], dkr[u * 4 + r], dki[u * 4 + r], ekin);
                 }
