@@ -99,7 +99,7 @@ struct lise_ctx {
     double g_used = 0.0;       // coupling of Delta = -g kappa (bare or regularised)
     int remove_phase = 0;      // Eq. (sp_en): evolve with H - eta_j
     double* eta = nullptr;     // [M] eta_j of the vector the current H application acts on
-    double* eta_part = nullptr;  // [chunk][plane blocks] partial sums of the eta pass
+    double* eta_part = nullptr;  // partial sums of the eta pass: [chunk][plane blocks] ([..][waves] forward-only)
     long long eta_part_cap = 0;
     double* ez_part[2] = {nullptr, nullptr};  // z-kinetic partials of the eta pass, per G buffer
     long long ez_cap = 0;
@@ -214,6 +214,13 @@ int plane_grid_x(const lise_ctx* c) {
     }
     if (c->mfma_xy) return c->lat.nz;
     return c->lat.nz / c->zb;
+}
+
+// The forward-only pass walks kEtaJg qpwfs per workgroup and writes one
+// partial sum per wave, plane block and qpwf.
+constexpr int kEtaJg = 4;
+long long etaxy_parts(const lise_ctx* c) {
+    return (long long)plane_grid_x(c) * (plane_block_of((int)c->esz / 2, c->lat.nx) / 64);
 }
 
 // Allow every kernel that takes dynamic LDS to use the device's whole LDS,
@@ -340,7 +347,8 @@ int configure(lise_ctx* c) {
         c->slot_cap = (int)dens_slots;
     }
     if (c->remove_phase) {
-        const long long need = c->chunk * (long long)(nz / c->zb);
+        const long long need =
+            c->chunk * std::max<long long>(nz / c->zb, c->fast_xy && c->fast_z ? etaxy_parts(c) : 0);
         if (c->eta_part_cap < need) {
             dfree(reinterpret_cast<void**>(&c->eta_part));
             CHK(dalloc(c, reinterpret_cast<void**>(&c->eta_part), (size_t)need * sizeof(double)));
@@ -595,10 +603,11 @@ int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k, const do
     const int nblk = plane_grid_x(c);
     const double a3 = c->lat.a * c->lat.a * c->lat.a;
     if (ez) {
+        e.jg = kEtaJg;
         CHK((launch_kp_t<T, KP_ETAXY>(c, e, j0, k, 3)));
         const long long nez = (long long)c->C * c->lat.nx * c->lat.ny * kz_lanes_of(c->lat.nz);
-        hipLaunchKernelGGL(eta_reduce2_kernel, dim3((unsigned)k), dim3(256), 0, c->stream, c->eta_part, nblk, ez, nez,
-                           a3, c->eta + j0);
+        hipLaunchKernelGGL(eta_reduce2_kernel, dim3((unsigned)k), dim3(256), 0, c->stream, c->eta_part,
+                           (int)etaxy_parts(c), ez, nez, a3, c->eta + j0);
         return check_launch(c, "eta_reduce2_kernel");
     }
     CHK((launch_kp_t<T, KP_ETA>(c, e, j0, k, 3)));

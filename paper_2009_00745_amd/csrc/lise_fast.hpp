@@ -252,10 +252,13 @@ constexpr bool plane_stream_hint() {
     return plane_stream_hint_of((int)sizeof(T), N);
 }
 
+__host__ __device__ constexpr int plane_block_of(int esz, int N) {
+    return (plane_zp_of(esz, N) * plane_lanes_of(esz, N) * N + 63) / 64 * 64;
+}
+
 template <typename T, int N>
 constexpr int plane_block() {
-    constexpr int t = plane_zp<T, N>() * plane_lanes<T, N>() * N;
-    return (t + 63) / 64 * 64;
+    return plane_block_of((int)sizeof(T), N);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,8 +511,18 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             }
             __syncthreads();
         }
+        if constexpr (MODE == KP_ETAXY) {
+            // one partial sum per wave and qpwf (fixed-order butterfly; lane 0
+            // holds the wave's sum), [qpwf][plane block][wave]
+            double v = ekin;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((tid & 63) == 0) a.epart[((long long)jl * gridDim.x + blockIdx.x) * (nth >> 6) + (tid >> 6)] = v;
+            ekin = 0.0;
+        }
     }
-    if (MODE == KP_KINETIC || MODE == KP_ETA || MODE == KP_ETAXY) {
+    if constexpr (MODE == KP_ETAXY) return;
+    if (MODE == KP_KINETIC || MODE == KP_ETA) {
         double* red = reinterpret_cast<double*>(smem_raw);
         red[tid] = ekin;
         __syncthreads();
