@@ -202,7 +202,8 @@ bool fast_side(int n) {
 size_t fast_kp_lds(const lise_ctx* c) {
     const size_t n = c->lat.nx;
     const size_t zp = plane_zp_of((int)c->esz / 2, (int)n);
-    return (n + zp * 2 * n * (n + 1)) * c->esz;
+    const bool natural = !plane_stream_hint_of((int)c->esz / 2, (int)n);
+    return (n + zp * 2 * n * (n + 1) + (natural ? zp * 2 * n * n : 0)) * c->esz;
 }
 
 // workgroups along z of one plane-kernel launch (= partial sums per qpwf of

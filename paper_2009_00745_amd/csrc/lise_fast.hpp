@@ -361,25 +361,60 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// xy planes of a square lattice side N; one workgroup per z-plane and qpwf
-// group, 4N active threads (row = tid/4, lane s = tid%4).
+// xy planes of a square lattice side N; one workgroup per z-plane (ZP planes
+// in float32 at N = 8, 20) and group of jg qpwfs; a row of the plane is spread
+// over L lanes (lane s holds the points s + L q).
+//
+// Global memory order.  Where L points of a row fill whole 128-byte lines
+// (plane_stream_hint), every lane reads and writes its own points of the
+// state arrays directly.  Elsewhere (NAT: N = 20 on 4 lanes, N = 16, 24 on 8
+// lanes in float32, N = 8, 20 in float64) a wave instruction in that order
+// would touch 32-64 bytes of many lines, which measured at 3.0-4.3 TB/s
+// against 4.9-5.5 for whole lines.  There the workgroup reads x in natural
+// order (thread t: points t + i * nth of its contiguous ZP-plane block) into
+// LDS, the row transform takes its points from LDS, and after the inverse
+// row transform the result goes back to LDS so that the epilogue runs in
+// natural order as well: every global access of the kernel is then a
+// contiguous run of the wave's width.
+
+template <typename T, int N>
+constexpr bool plane_natural() {
+    return !plane_stream_hint<T, N>();
+}
 
 template <typename T, int N>
 constexpr size_t kp_fast_lds() {
-    return (size_t)(N + plane_zp<T, N>() * 2 * N * (N + 1)) * sizeof(cpx<T>);
+    constexpr int ZP = plane_zp<T, N>();
+    return (size_t)(N + ZP * 2 * N * (N + 1) + (plane_natural<T, N>() ? ZP * 2 * N * N : 0)) * sizeof(cpx<T>);
 }
 
 #ifndef LISE_KP_MIN_WAVES
 #define LISE_KP_MIN_WAVES 1
 #endif
 
+// the local part of <f|H f> at one point rpt of the lattice (forward-only
+// eta pass): (V - mu_a)|u|^2 - (V - mu_b)|v|^2 + 2 s Re(Delta u^* v)
+template <typename T>
+__device__ __forceinline__ double eta_local(const KPArgs<T>& a, int pr, double sg, long long rpt, cpx<T> u, cpx<T> v) {
+    const double V = a.V[rpt];
+    const double Dr = sg * a.D[2 * rpt], Di = sg * a.D[2 * rpt + 1];
+    const double ur = double(u.re), ui = double(u.im);
+    const double vr = double(v.re), vi = double(v.im);
+    return (V - a.mu_a[pr]) * (ur * ur + ui * ui) - (V - a.mu_b[pr]) * (vr * vr + vi * vi) +
+           2.0 * (Dr * (ur * vr + ui * vi) - Di * (ur * vi - ui * vr));
+}
+
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
     constexpr int L = plane_lanes<T, N>();
     constexpr int P = N / L;
     constexpr bool NT = plane_stream_hint<T, N>();
+    constexpr bool NAT = plane_natural<T, N>();
     constexpr int LD = N + 1;
     constexpr int ZP = plane_zp<T, N>();
+    constexpr int NTH = plane_block<T, N>();
+    constexpr int NN = N * N;
+    constexpr int PN = NAT ? (ZP * NN + NTH - 1) / NTH : P;   // points per thread in the epilogue
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
     const int tid = threadIdx.x;
@@ -397,6 +432,11 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     }
     cpx<T>* La = tab + N + (ZP > 1 && act ? zi : 0) * 2 * N * LD;
     cpx<T>* Lb = La + N * LD;
+    // natural-order copies of x for the ZP planes (NAT only)
+    cpx<T>* Xa = tab + N + ZP * 2 * N * LD;
+    cpx<T>* Xb = Xa + ZP * NN;
+    const int z0 = blockIdx.x * ZP;                   // first plane of the workgroup
+    const int nvalid = min(ZP, a.nz - z0) * NN;       // natural-order points of the workgroup
     const int row = tl / L;
     const int s = tl % L;
     const int brs = bitrev(s, L);
@@ -406,9 +446,9 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     const int jend = min(a.kcount, jbeg + a.jg);
     const T cdt = T(a.dt / 48.0);
     const cpx<T> coef = mk(T(a.coef_re), T(a.coef_im));
-    double dn[P], dkr[P], dki[P];
+    double dn[PN], dkr[PN], dki[PN];
 #pragma unroll
-    for (int q = 0; q < P; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
+    for (int q = 0; q < PN; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
     double ekin = 0.0;
     __syncthreads();
 
@@ -418,14 +458,33 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
+            // natural order: the workgroup's ZP planes are contiguous from z0
+            const long long noffa = ((jgl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
+            const long long noffb = ((jgl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
             cpx<T> xa[P], xb[P], fa[P], fb[P];
+            if constexpr (NAT) {
+#pragma unroll
+                for (int i = 0; i < PN; ++i) {
+                    const int p = tid + i * NTH;
+                    if (p < nvalid) {
+                        Xa[p] = a.in[noffa + p];
+                        Xb[p] = a.in[noffb + p];
+                    }
+                }
+                __syncthreads();
+            }
             if (act) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    fa[q] = ld_hint<T, NT>(a.in + offa + row * N + s + L * q);
-                    fb[q] = ld_hint<T, NT>(a.in + offb + row * N + s + L * q);
-                    xa[q] = fa[q];
-                    xb[q] = fb[q];
+                    if constexpr (NAT) {
+                        xa[q] = Xa[zi * NN + row * N + s + L * q];
+                        xb[q] = Xb[zi * NN + row * N + s + L * q];
+                    } else {
+                        fa[q] = ld_hint<T, NT>(a.in + offa + row * N + s + L * q);
+                        fb[q] = ld_hint<T, NT>(a.in + offb + row * N + s + L * q);
+                        xa[q] = fa[q];
+                        xb[q] = fb[q];
+                    }
                 }
                 lane_fwd<T, P, L>(xa, tab, s);
                 lane_fwd<T, P, L>(xb, tab, s);
@@ -475,18 +534,19 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             if constexpr (MODE == KP_ETAXY) {
                 // the local part of <f|H f> from the point values: (V - mu_a)|u|^2
                 // - (V - mu_b)|v|^2 + 2 s Re(Delta u^* v)
-                if (act) {
-                    const T sg = T(a.sgn[pr]);
+                const double sg = double(a.sgn[pr]);
+                if constexpr (NAT) {
 #pragma unroll
-                    for (int q = 0; q < P; ++q) {
-                        const long long rpt = (long long)z * nxy + row * N + s + L * q;
-                        const double V = a.V[rpt];
-                        const double Dr = double(sg) * a.D[2 * rpt], Di = double(sg) * a.D[2 * rpt + 1];
-                        const double ur = double(fa[q].re), ui = double(fa[q].im);
-                        const double vr = double(fb[q].re), vi = double(fb[q].im);
-                        ekin += (V - a.mu_a[pr]) * (ur * ur + ui * ui) - (V - a.mu_b[pr]) * (vr * vr + vi * vi) +
-                                2.0 * (Dr * (ur * vr + ui * vi) - Di * (ur * vi - ui * vr));
+                    for (int i = 0; i < PN; ++i) {
+                        const int p = tid + i * NTH;
+                        if (p < nvalid)
+                            ekin += eta_local(a, pr, sg, (long long)z0 * nxy + p, Xa[p], Xb[p]);
                     }
+                    __syncthreads();   // Xa, Xb are rewritten by the next pair
+                } else if (act) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q)
+                        ekin += eta_local(a, pr, sg, (long long)z * nxy + row * N + s + L * q, fa[q], fb[q]);
                 }
                 continue;   // the next pair reuses La, Lb only after the barrier above
             }
@@ -498,6 +558,33 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                 }
                 lane_inv<T, P, L>(xa, tab, s);
                 lane_inv<T, P, L>(xb, tab, s);
+            }
+            if constexpr (NAT) {
+                // the xy-term to LDS in natural order (each plane's La, Lb
+                // hold N x N points there), then the epilogue in natural order
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        La[row * N + s + L * q] = xa[q];
+                        Lb[row * N + s + L * q] = xb[q];
+                    }
+                }
+                __syncthreads();
+                const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
+                const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
+#pragma unroll
+                for (int i = 0; i < PN; ++i) {
+                    const int p = tid + i * NTH;
+                    if (p < nvalid) {
+                        const int pz = p / NN, r = p - pz * NN;
+                        const cpx<T>* Lz = tab + N + pz * 2 * N * LD;
+                        point_epilogue<T, MODE, true, false>(a, pr, Lz[r], Lz[N * LD + r], Xa[p], Xb[p], noffa + p,
+                                                             noffb + p, (long long)z0 * nxy + p, lofa + p, lofb + p,
+                                                             coef, cdt, ej, dn[i], dkr[i], dki[i], ekin);
+                    }
+                }
+            } else if (act) {
                 const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z) * nxy;
                 const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z) * nxy;
 #pragma unroll
@@ -506,7 +593,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                     // the plane kernels never run fused: the z-term is always in G
                     const long long ea = offa + pt, eb = offb + pt;
                     point_epilogue<T, MODE, true, NT>(a, pr, xa[q], xb[q], fa[q], fb[q], ea, eb, (long long)z * nxy + pt,
-                                                  lofa + pt, lofb + pt, coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
+                                                      lofa + pt, lofb + pt, coef, cdt, ej, dn[q], dkr[q], dki[q], ekin);
                 }
             }
             __syncthreads();
@@ -535,7 +622,25 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
         if (tid == 0) a.epart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
         return;
     }
-    if (a.dens_src && act) {
+    if constexpr (NAT) {
+        if (a.dens_src) {
+            double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z0 * nxy;
+#pragma unroll
+            for (int i = 0; i < PN; ++i) {
+                const int p = tid + i * NTH;
+                if (p >= nvalid) continue;
+                if (a.accumulate) {
+                    base[p] += dn[i];
+                    base[N3 + p] += dkr[i];
+                    base[2 * N3 + p] += dki[i];
+                } else {
+                    base[p] = dn[i];
+                    base[N3 + p] = dkr[i];
+                    base[2 * N3 + p] = dki[i];
+                }
+            }
+        }
+    } else if (a.dens_src && act) {
         double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
