@@ -201,19 +201,14 @@ bool fast_side(int n) {
 
 size_t fast_kp_lds(const lise_ctx* c) {
     const size_t n = c->lat.nx;
-    const size_t zp = plane_zp_of((int)c->esz / 2, (int)n);
     const bool natural = !plane_stream_hint_of((int)c->esz / 2, (int)n);
-    return (n + zp * 2 * n * (n + 1) + (natural ? zp * 2 * n * n : 0)) * c->esz;
+    return (n + 2 * n * (n + 1) + (natural ? 2 * n * n : 0)) * c->esz;
 }
 
 // workgroups along z of one plane-kernel launch (= partial sums per qpwf of
 // the reducing modes)
 int plane_grid_x(const lise_ctx* c) {
-    if (c->fast_xy) {
-        const int zp = plane_zp_of((int)c->esz / 2, c->lat.nx);
-        return (c->lat.nz + zp - 1) / zp;
-    }
-    if (c->mfma_xy) return c->lat.nz;
+    if (c->fast_xy || c->mfma_xy) return c->lat.nz;
     return c->lat.nz / c->zb;
 }
 
@@ -664,11 +659,11 @@ int slots_used(const lise_ctx* c, long long count) {
 // average, then fields at time t.
 // toff: time offset from the system's device-side time t_n
 int launch_fields(lise_ctx* c, int nslots, const double* avg_with, double* dens, double* V, double* D, double toff) {
-    dim3 grid((unsigned)((c->N + kThreads - 1) / kThreads));
+    dim3 grid((unsigned)((c->N + kFieldPts - 1) / kFieldPts));
     hipEvent_t ev;
     prof_begin(c, 2, &ev);
-    hipLaunchKernelGGL(fields_kernel, grid, dim3(kThreads), 0, c->stream, c->dpart, nslots, c->N, avg_with, dens, V,
-                       D, field_params(c), c->dtime, toff, c->bad);
+    hipLaunchKernelGGL(fields_kernel, grid, dim3(kFieldPts * kFieldGroups), 0, c->stream, c->dpart, nslots, c->N,
+                       avg_with, dens, V, D, field_params(c), c->dtime, toff, c->bad);
     prof_end(c, 2, ev);
     return check_launch(c, "fields_kernel");
 }

@@ -916,23 +916,43 @@ __device__ __forceinline__ double ext_potential(const FieldParams& f, long long 
 
 // The time comes from device memory (tdev[0] + toff) so that a captured
 // graph of whole steps stays valid on every replay.
-__global__ void __launch_bounds__(256) fields_kernel(const double* __restrict__ dpart, int nslots, long long N,
-                                                     const double* __restrict__ avg_with,
-                                                     double* __restrict__ dens_out, double* __restrict__ V,
-                                                     double* __restrict__ D, FieldParams fp,
-                                                     const double* __restrict__ tdev, double toff,
-                                                     int* __restrict__ bad) {
-    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
+// A workgroup takes kFieldPts consecutive points; its kFieldGroups waves sum
+// the slots g, g + kFieldGroups, ... of those points (coalesced rows of the
+// slot array), and the first wave adds the group sums in order g = 0, 1, ...
+// (a fixed order: bitwise reproducible), then forms the fields.
+constexpr int kFieldPts = 64;
+constexpr int kFieldGroups = 16;
+__global__ void __launch_bounds__(kFieldPts * kFieldGroups) fields_kernel(
+    const double* __restrict__ dpart, int nslots, long long N, const double* __restrict__ avg_with,
+    double* __restrict__ dens_out, double* __restrict__ V, double* __restrict__ D, FieldParams fp,
+    const double* __restrict__ tdev, double toff, int* __restrict__ bad) {
+    __shared__ double part[3][kFieldGroups][kFieldPts];
+    const int pt = threadIdx.x % kFieldPts, g = threadIdx.x / kFieldPts;
+    const long long r = (long long)blockIdx.x * kFieldPts + pt;
+    if (nslots > 0) {
+        double n = 0.0, kr = 0.0, ki = 0.0;
+        if (r < N) {
+            for (int s = g; s < nslots; s += kFieldGroups) {
+                const double* b = dpart + (long long)s * 3 * N;
+                n += b[r];
+                kr += b[N + r];
+                ki += b[2 * N + r];
+            }
+        }
+        part[0][g][pt] = n;
+        part[1][g][pt] = kr;
+        part[2][g][pt] = ki;
+        __syncthreads();
+    }
+    if (g != 0 || r >= N) return;
     const double t = tdev[0] + toff;
     double n, kr, ki;
     if (nslots > 0) {
         n = kr = ki = 0.0;
-        for (int s = 0; s < nslots; ++s) {
-            const double* b = dpart + (long long)s * 3 * N;
-            n += b[r];
-            kr += b[N + r];
-            ki += b[2 * N + r];
+        for (int h = 0; h < kFieldGroups; ++h) {
+            n += part[0][h][pt];
+            kr += part[1][h][pt];
+            ki += part[2][h][pt];
         }
     } else {
         n = dens_out[r];

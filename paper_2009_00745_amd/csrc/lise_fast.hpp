@@ -218,27 +218,6 @@ __host__ __device__ constexpr int plane_lanes_of(int esz, int N) {
     return L;
 }
 
-// xy-planes per workgroup: in float32, where a plane's L*N lanes leave a wave
-// partly idle (N = 8: 32 lanes, N = 20: 80), a workgroup takes 2 or 4 planes
-// (20^3: 3% faster; in float64 the larger workgroups measured 7% slower)
-__host__ __device__ constexpr int plane_zp_of(int esz, int N) {
-    if (esz == 8) return 1;
-    const int t = plane_lanes_of(esz, N) * N;
-    for (int zp = 1; zp <= 4; zp *= 2)
-        if ((zp * t) % 64 == 0 && zp * t <= 1024) return zp;
-    return 1;
-}
-
-template <typename T, int N>
-constexpr int plane_lanes() {
-    return plane_lanes_of((int)sizeof(T), N);
-}
-
-template <typename T, int N>
-constexpr int plane_zp() {
-    return plane_zp_of((int)sizeof(T), N);
-}
-
 // nontemporal hints in the plane kernel: one load instruction of a wave reads
 // L consecutive points of each of its rows, so the hint is taken only where
 // those L points and a whole row are multiples of a 128-byte line (every
@@ -252,8 +231,14 @@ constexpr bool plane_stream_hint() {
     return plane_stream_hint_of((int)sizeof(T), N);
 }
 
+template <typename T, int N>
+constexpr int plane_lanes() {
+    return plane_lanes_of((int)sizeof(T), N);
+}
+
+// one xy-plane per workgroup: L lanes per row, rounded up to whole waves
 __host__ __device__ constexpr int plane_block_of(int esz, int N) {
-    return (plane_zp_of(esz, N) * plane_lanes_of(esz, N) * N + 63) / 64 * 64;
+    return (plane_lanes_of(esz, N) * N + 63) / 64 * 64;
 }
 
 template <typename T, int N>
@@ -361,9 +346,9 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// xy planes of a square lattice side N; one workgroup per z-plane (ZP planes
-// in float32 at N = 8, 20) and group of jg qpwfs; a row of the plane is spread
-// over L lanes (lane s holds the points s + L q).
+// xy planes of a square lattice side N; one workgroup per z-plane and group
+// of jg qpwfs; a row of the plane is spread over L lanes (lane s holds the
+// points s + L q).
 //
 // Global memory order.  Where L points of a row fill whole 128-byte lines
 // (plane_stream_hint), every lane reads and writes its own points of the
@@ -371,8 +356,8 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
 // lanes in float32, N = 8, 20 in float64) a wave instruction in that order
 // would touch 32-64 bytes of many lines, which measured at 3.0-4.3 TB/s
 // against 4.9-5.5 for whole lines.  There the workgroup reads x in natural
-// order (thread t: points t + i * nth of its contiguous ZP-plane block) into
-// LDS, the row transform takes its points from LDS, and after the inverse
+// order (thread t: points t + i * nth of the plane) into LDS, the row
+// transform takes its points from LDS, and after the inverse
 // row transform the result goes back to LDS so that the epilogue runs in
 // natural order as well: every global access of the kernel is then a
 // contiguous run of the wave's width.
@@ -384,8 +369,7 @@ constexpr bool plane_natural() {
 
 template <typename T, int N>
 constexpr size_t kp_fast_lds() {
-    constexpr int ZP = plane_zp<T, N>();
-    return (size_t)(N + ZP * 2 * N * (N + 1) + (plane_natural<T, N>() ? ZP * 2 * N * N : 0)) * sizeof(cpx<T>);
+    return (size_t)(N + 2 * N * (N + 1) + (plane_natural<T, N>() ? 2 * N * N : 0)) * sizeof(cpx<T>);
 }
 
 #ifndef LISE_KP_MIN_WAVES
@@ -411,34 +395,22 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     constexpr bool NT = plane_stream_hint<T, N>();
     constexpr bool NAT = plane_natural<T, N>();
     constexpr int LD = N + 1;
-    constexpr int ZP = plane_zp<T, N>();
     constexpr int NTH = plane_block<T, N>();
     constexpr int NN = N * N;
-    constexpr int PN = NAT ? (ZP * NN + NTH - 1) / NTH : P;   // points per thread in the epilogue
+    constexpr int PN = NAT ? (NN + NTH - 1) / NTH : P;   // points per thread in the epilogue
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
     for (int i = tid; i < N; i += nth) tab[i] = twN[i];
-    // plane zi of the workgroup's ZP planes; its lines over L lanes (with one
-    // plane per workgroup the index arithmetic reduces to the plain form)
-    int zi = 0, tl = tid, z = blockIdx.x;
-    bool act = tid < L * N;
-    if constexpr (ZP > 1) {
-        zi = tid / (L * N);
-        tl = tid - zi * (L * N);
-        z = blockIdx.x * ZP + zi;
-        act = zi < ZP && z < a.nz;
-    }
-    cpx<T>* La = tab + N + (ZP > 1 && act ? zi : 0) * 2 * N * LD;
+    const int z = blockIdx.x;
+    const bool act = tid < L * N;   // lanes of the row transforms
+    cpx<T>* La = tab + N;
     cpx<T>* Lb = La + N * LD;
-    // natural-order copies of x for the ZP planes (NAT only)
-    cpx<T>* Xa = tab + N + ZP * 2 * N * LD;
-    cpx<T>* Xb = Xa + ZP * NN;
-    const int z0 = blockIdx.x * ZP;                   // first plane of the workgroup
-    const int nvalid = min(ZP, a.nz - z0) * NN;       // natural-order points of the workgroup
-    const int row = tl / L;
-    const int s = tl % L;
+    cpx<T>* Xa = Lb + N * LD;        // natural-order copy of x (NAT only)
+    cpx<T>* Xb = Xa + NN;
+    const int row = tid / L;
+    const int s = tid % L;
     const int brs = bitrev(s, L);
     constexpr long long nxy = (long long)N * N;
     const long long N3 = nxy * a.nz;
@@ -458,17 +430,14 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
         for (int pr = 0; pr < a.npair; ++pr) {
             const long long offa = ((jgl * a.C + a.ca[pr]) * a.nz + z) * nxy;
             const long long offb = ((jgl * a.C + a.cb[pr]) * a.nz + z) * nxy;
-            // natural order: the workgroup's ZP planes are contiguous from z0
-            const long long noffa = ((jgl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
-            const long long noffb = ((jgl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
             cpx<T> xa[P], xb[P], fa[P], fb[P];
             if constexpr (NAT) {
 #pragma unroll
                 for (int i = 0; i < PN; ++i) {
                     const int p = tid + i * NTH;
-                    if (p < nvalid) {
-                        Xa[p] = a.in[noffa + p];
-                        Xb[p] = a.in[noffb + p];
+                    if (p < NN) {
+                        Xa[p] = a.in[offa + p];
+                        Xb[p] = a.in[offb + p];
                     }
                 }
                 __syncthreads();
@@ -477,8 +446,8 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     if constexpr (NAT) {
-                        xa[q] = Xa[zi * NN + row * N + s + L * q];
-                        xb[q] = Xb[zi * NN + row * N + s + L * q];
+                        xa[q] = Xa[row * N + s + L * q];
+                        xb[q] = Xb[row * N + s + L * q];
                     } else {
                         fa[q] = ld_hint<T, NT>(a.in + offa + row * N + s + L * q);
                         fb[q] = ld_hint<T, NT>(a.in + offb + row * N + s + L * q);
@@ -539,8 +508,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
 #pragma unroll
                     for (int i = 0; i < PN; ++i) {
                         const int p = tid + i * NTH;
-                        if (p < nvalid)
-                            ekin += eta_local(a, pr, sg, (long long)z0 * nxy + p, Xa[p], Xb[p]);
+                        if (p < NN) ekin += eta_local(a, pr, sg, (long long)z * nxy + p, Xa[p], Xb[p]);
                     }
                     __syncthreads();   // Xa, Xb are rewritten by the next pair
                 } else if (act) {
@@ -560,8 +528,8 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                 lane_inv<T, P, L>(xb, tab, s);
             }
             if constexpr (NAT) {
-                // the xy-term to LDS in natural order (each plane's La, Lb
-                // hold N x N points there), then the epilogue in natural order
+                // the xy-term to LDS in natural order (La, Lb hold N x N
+                // points there), then the epilogue in natural order
                 __syncthreads();
                 if (act) {
 #pragma unroll
@@ -571,18 +539,15 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                     }
                 }
                 __syncthreads();
-                const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z0) * nxy;
-                const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z0) * nxy;
+                const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z) * nxy;
+                const long long lofb = (((long long)jl * a.C + a.cb[pr]) * a.nz + z) * nxy;
 #pragma unroll
                 for (int i = 0; i < PN; ++i) {
                     const int p = tid + i * NTH;
-                    if (p < nvalid) {
-                        const int pz = p / NN, r = p - pz * NN;
-                        const cpx<T>* Lz = tab + N + pz * 2 * N * LD;
-                        point_epilogue<T, MODE, true, false>(a, pr, Lz[r], Lz[N * LD + r], Xa[p], Xb[p], noffa + p,
-                                                             noffb + p, (long long)z0 * nxy + p, lofa + p, lofb + p,
-                                                             coef, cdt, ej, dn[i], dkr[i], dki[i], ekin);
-                    }
+                    if (p < NN)
+                        point_epilogue<T, MODE, true, false>(a, pr, La[p], Lb[p], Xa[p], Xb[p], offa + p, offb + p,
+                                                             (long long)z * nxy + p, lofa + p, lofb + p, coef, cdt, ej,
+                                                             dn[i], dkr[i], dki[i], ekin);
                 }
             } else if (act) {
                 const long long lofa = (((long long)jl * a.C + a.ca[pr]) * a.nz + z) * nxy;
@@ -624,11 +589,11 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     }
     if constexpr (NAT) {
         if (a.dens_src) {
-            double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z0 * nxy;
+            double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
 #pragma unroll
             for (int i = 0; i < PN; ++i) {
                 const int p = tid + i * NTH;
-                if (p >= nvalid) continue;
+                if (p >= NN) continue;
                 if (a.accumulate) {
                     base[p] += dn[i];
                     base[N3 + p] += dkr[i];
