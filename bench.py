@@ -124,6 +124,34 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     return ctx, t2 - t1, prof
 
 
+def reduced_error(name, steps, M):
+    """Density error of the float32 forms against float64 on a reduced instance of a
+    workload whose float64 state does not fit at full size: the same lattice and
+    recipe with fewer qpwfs, compared after the same number of ABM steps."""
+    import torch
+    import workloads as wl
+    make = {"cfg3": wl.config3, "cfg4": wl.config4}[name]
+    forms = {"cfg3": [("fp32", wl.FP32)],
+             "cfg4": [("fp32_register_fft", wl.FP32), ("fp32_mfma_bf16x3", wl.FP32_MFMA)]}[name]
+
+    def run(prec):
+        w = make(M=M, precision=prec)
+        ctx, _, _ = run_gpu(w, steps, 0, None, profile=False)
+        n, k = ctx.densities()
+        st = ctx.time()[1]
+        ctx.close()
+        torch.cuda.empty_cache()
+        return n, k, st
+
+    n64, k64, s64 = run(wl.FP64)
+    out = {"M": M, "after_steps": int(s64), "reference": "fp64 on the GPU (parity-tested against the oracle)"}
+    for label, prec in forms:
+        n, k, st = run(prec)
+        out[label] = {"n": float(np.linalg.norm(n - n64) / np.linalg.norm(n64)),
+                      "kappa": float(np.linalg.norm(k - k64) / np.linalg.norm(k64))} if st == s64 else None
+    return out
+
+
 def run_batched(nsys, steps, warmup, graph=1):
     """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced together,
     each on its own forked stream (with its own four-step graph replays when graph = 1)."""
@@ -254,6 +282,10 @@ def main():
                     help="skip the variant with the trivial phase removed (Eq. sp_en)")
     ap.add_argument("--batched", type=int, default=16,
                     help="number of independent systems in the batched variant (0 = skip; 64 = full workload)")
+    ap.add_argument("--reduced-error", type=int, default=0, metavar="M",
+                    help="cfg3/cfg4: also measure the float32 density error against float64 on the same "
+                         "workload with M qpwfs (4096 for cfg3, 1024 for cfg4 fit in float64)")
+    ap.add_argument("--reduced-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -368,6 +400,9 @@ def main():
             "after_steps": int(sp), "tuning": chosenp,
             "note": "eta by Parseval on the register-FFT path: the pass re-reads x once, 22 state arrays per step instead of 20"}
 
+    if args.reduced_error and args.workload in ("cfg3", "cfg4", "cfg4_fp32"):
+        variants["reduced_error"] = reduced_error(args.workload[:4], args.reduced_steps, args.reduced_error)
+
     if args.batched and args.workload == "cfg2":
         variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
 
@@ -381,7 +416,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w.functional.precision == 0 else "f32", "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.lattice.nx}^3 lattice, {w.M} two-component qpwfs, "
+        "config": {"workload": f"{w.name}: {w.lattice.nx}^3 lattice, {w.M} {'two' if C == 2 else 'four'}-component qpwfs, "
                                f"dt={w.dt}, {w.notes}",
                    "lattice": [w.lattice.nx, w.lattice.ny, w.lattice.nz], "n_qpwf": w.M,
                    "ncomp": C, "dt": w.dt, "tuning": tuning or "default"},
