@@ -74,6 +74,10 @@ APPLY_CASES = [
     (48, 48, 48, 1.0, 2, 2, 2, {}),
     (64, 64, 64, 1.0, 4, 1, 2, {}),
     (32, 32, 24, 0.9, 4, 2, 2, {"chunk_qpwf": 1, "jgroup": 1}),
+    # float32 planes whose rows are partial cache lines (natural-order path), ragged qpwf groups
+    (8, 8, 8, 1.0, 2, 5, 1, {"fused": -1}),
+    (20, 20, 20, 1.0, 2, 5, 1, {"jgroup": 2}),
+    (24, 24, 20, 1.0, 4, 3, 1, {"chunk_qpwf": 2, "jgroup": 1}),
 ]
 
 
@@ -221,6 +225,27 @@ def test_phase_removal_two_eta_passes_agree(lise):
         e = rel_l2(outs[0], outs[1])
         say(f"  rel L2 between the two eta passes {e:.3e}")
         assert e < 1e-12
+
+
+def test_phase_removal_full_eta_pass_on_register_plane_kernel(lise):
+    """Phase removal where the plane kernel is the register-FFT one but the z axis is not
+    (nz = 12): the full eta recomputation runs on that plane kernel, in the lane order
+    (16^2 FP64) and in the natural order (20^2 FP64 and FP32), against the oracle."""
+    for n, prec, tol in ((16, wl.FP64, 1e-11), (20, wl.FP64, 1e-11), (20, wl.FP32, 1e-5)):
+        lat = wl.Lattice(n, n, 12, 1.0)
+        fn = wl.Functional(ncomp=2, mu_up=0.5, mu_dn=0.5, beta=0.37, g=2.0, w=2.0, ext_A=-0.025, ext_w=3.0,
+                           ext_r0=(2.0, 3.0, 4.0), ext_t_on=0.0, remove_phase=1, precision=prec)
+        M = 12
+        w = wl.Workload(f"eta_full_{n}x{n}x12_p{prec}", lat, fn, M, 0.002, 6,
+                        wl.uniform_bcs(lat, fn, M, 0.3, 0.5, eps=1e-2))
+        say(f"step {w.name} phase removed, full eta pass, 6 steps")
+        got, dn, dk, t, s, obs, ev = run_pair(lise, w, 6)
+        n0, k0 = oracle.densities(ev.y, fn)
+        e = (rel_l2(dn, n0), rel_l2(dk, k0))
+        if prec == wl.FP64:
+            e = (rel_l2(got, ev.y),) + e
+        say(f"  rel L2: {e}")
+        assert max(e) < tol
 
 
 def test_phase_removal_frozen_eigenvectors_stay_put(lise):
