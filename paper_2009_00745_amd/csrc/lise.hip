@@ -76,6 +76,8 @@ struct lise_ctx {
     void* tw = nullptr;
     double* red = nullptr;     // reduction partials (observables)
     long long red_cap = 0;
+    double* pz_part = nullptr;  // per-workgroup z-momentum sums (observables)
+    long long pz_cap = 0;
     double* norms = nullptr;
     double* norms0 = nullptr;
     int* bad = nullptr;
@@ -962,22 +964,29 @@ int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_
     return rc;
 }
 
+// Kinetic energy of the current state (plane kernel in mode KP_KINETIC).  With
+// pxy (register-FFT plane kernel only) the same pass also returns the
+// Parseval sums of the total current along x and y over the v components:
+// pxy[0] = sum m_x |F_xy v|^2, pxy[1] = sum m_y |F_xy v|^2 (signed indices).
 template <typename T>
-int kinetic_energy_t(lise_ctx* c, double* ekin) {
+int kinetic_energy_t(lise_ctx* c, double* ekin, double* pxy = nullptr) {
+    if (pxy && !c->fast_xy) return fail(c, LISE_E_STATE, "current sums need the register-FFT plane kernel");
     KPArgs<T> a = kp_base<T>(c);
     a.V = c->V_cur;
     a.D = c->D_cur;
     a.in = ycur<T>(c);
     a.G = reinterpret_cast<const cpx<T>*>(c->G);
     const long long nwg_per = (long long)plane_grid_x(c) * ((c->chunk + c->jg - 1) / c->jg);
-    if (c->red_cap < nwg_per) {
+    const long long need = (pxy ? 3 : 1) * nwg_per;
+    if (c->red_cap < need) {
         dfree(reinterpret_cast<void**>(&c->red));
-        CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)std::max<long long>(nwg_per, 4096) * sizeof(double)));
-        c->red_cap = std::max<long long>(nwg_per, 4096);
+        CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)std::max<long long>(need, 4096) * sizeof(double)));
+        c->red_cap = std::max<long long>(need, 4096);
     }
     a.epart = c->red;
-    std::vector<double> h(nwg_per);
-    double sum = 0.0;
+    a.ppart = pxy ? c->red + nwg_per : nullptr;
+    std::vector<double> h(need);
+    double sum = 0.0, sx = 0.0, sy = 0.0;
     for (long long j0 = 0; j0 < c->M; j0 += c->chunk) {
         const int k = (int)std::min<long long>(c->chunk, c->M - j0);
         if (!c->fused) CHK(launch_kz_t<T>(c, a.in, j0, k, c->Gbuf[0], c->stream));
@@ -985,10 +994,66 @@ int kinetic_energy_t(lise_ctx* c, double* ekin) {
         CHK((launch_kp_t<T, KP_KINETIC>(c, a, j0, k, 3)));
         const long long nwg = (long long)plane_grid_x(c) * ((k + c->jg - 1) / c->jg);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->red, nwg * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (pxy)
+            HIPCHK(c, hipMemcpyAsync(h.data() + nwg_per, a.ppart, 2 * nwg * sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (long long i = 0; i < nwg; ++i) sum += h[i];
+        if (pxy)
+            for (long long i = 0; i < nwg; ++i) {
+                sx += h[nwg_per + 2 * i];
+                sy += h[nwg_per + 2 * i + 1];
+            }
     }
     *ekin = sum * c->lat.a * c->lat.a * c->lat.a;
+    if (pxy) {
+        pxy[0] = sx;
+        pxy[1] = sy;
+    }
+    return LISE_OK;
+}
+
+// Parseval sum of the total current along z over the v components,
+// sum m_z |F_z v|^2 (register-FFT z kernel only).
+template <typename T, int NZ>
+void launch_pz_n(const KZFastArgs<T>& f, double* part, unsigned nblk, hipStream_t st) {
+    hipLaunchKernelGGL((pz_kernel<T, NZ>), dim3(nblk), dim3(kThreads), 0, st, f, part);
+}
+
+template <typename T>
+int momentum_z_t(lise_ctx* c, double* pz) {
+    if (!c->fast_z) return fail(c, LISE_E_STATE, "z current sum needs the register-FFT z kernel");
+    KZFastArgs<T> f;
+    std::memset(&f, 0, sizeof(f));
+    f.nxy = (long long)c->lat.nx * c->lat.ny;
+    f.ncols = c->M * c->C * f.nxy;
+    f.j0 = 0;
+    f.C = c->C;
+    f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
+    f.in = ycur<T>(c);
+    f.nu = c->C == 2 ? 1 : 2;
+    const long long nblk = (f.ncols + kThreads - 1) / kThreads;
+    if (c->pz_cap < nblk) {
+        dfree(reinterpret_cast<void**>(&c->pz_part));
+        CHK(dalloc(c, reinterpret_cast<void**>(&c->pz_part), (size_t)nblk * sizeof(double)));
+        c->pz_cap = nblk;
+    }
+    switch (c->lat.nz) {
+        case 8: launch_pz_n<T, 8>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        case 16: launch_pz_n<T, 16>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        case 20: launch_pz_n<T, 20>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        case 24: launch_pz_n<T, 24>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        case 32: launch_pz_n<T, 32>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        case 48: launch_pz_n<T, 48>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+        default: launch_pz_n<T, 64>(f, c->pz_part, (unsigned)nblk, c->stream); break;
+    }
+    CHK(check_launch(c, "pz_kernel"));
+    std::vector<double> h(nblk);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->pz_part, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0.0;
+    for (long long i = 0; i < nblk; ++i) s += h[i];
+    *pz = s;
     return LISE_OK;
 }
 
@@ -1085,7 +1150,12 @@ int observables_t(lise_ctx* c, lise_obs* o) {
     for (int b = 0; b < nblk; ++b)
         for (int k = 0; k < kNObs; ++k) s[k] += h[b * kNObs + k];
     double ekin = 0.0;
-    CHK(kinetic_energy_t<T>(c, &ekin));
+    // with the register-FFT kernels on both axes the total current comes from
+    // Parseval sums (the kinetic pass gives x and y, one more pass over the v
+    // components z) instead of the current-density field
+    const bool parseval_p = c->fast_xy && c->fast_z;
+    double pxy[2] = {0.0, 0.0};
+    CHK(kinetic_energy_t<T>(c, &ekin, parseval_p ? pxy : nullptr));
     const double a3 = c->lat.a * c->lat.a * c->lat.a;
     std::memset(o, 0, sizeof(*o));
     o->t = c->t;
@@ -1113,16 +1183,31 @@ int observables_t(lise_ctx* c, lise_obs* o) {
     o->norm_drift_max = mx;
     o->norm_drift_mean = c->M ? mean / c->M : 0.0;
     // total current and centre-of-mass velocity (Eq. j, Eq. vel with m = hbar = 1)
-    CHK(current_t<T>(c, c->dens_tmp));
-    std::vector<double> jh(3 * c->N);
-    HIPCHK(c, hipMemcpyAsync(jh.data(), c->dens_tmp, jh.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 3; ++k) {
-        double sum = 0.0;
-        for (long long r = 0; r < c->N; ++r) sum += jh[k * c->N + r];
-        o->P[k] = a3 * sum;
-        o->v_cm[k] = o->N != 0.0 ? o->P[k] / o->N : 0.0;
+    if (parseval_p) {
+        // sum_r Im(v^* d_a v) = (2 pi / L_a) sum_k m_a |F v|^2 / (transform size):
+        // the xy sums come from 2D transforms of the planes, the z sum from 1D
+        // transforms of the columns
+        double sz = 0.0;
+        CHK(momentum_z_t<T>(c, &sz));
+        const double pi = 3.14159265358979323846;
+        const double w = c->C == 2 ? c->fn.w : 1.0;
+        const double nxy = (double)c->lat.nx * c->lat.ny;
+        o->P[0] = -w * a3 * (2.0 * pi / (c->lat.nx * c->lat.a)) * pxy[0] / nxy;
+        o->P[1] = -w * a3 * (2.0 * pi / (c->lat.ny * c->lat.a)) * pxy[1] / nxy;
+        o->P[2] = -w * a3 * (2.0 * pi / (c->lat.nz * c->lat.a)) * sz / c->lat.nz;
+    } else {
+        CHK(current_t<T>(c, c->dens_tmp));
+        std::vector<double> jh(3 * c->N);
+        HIPCHK(c, hipMemcpyAsync(jh.data(), c->dens_tmp, jh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int k = 0; k < 3; ++k) {
+            double sum = 0.0;
+            for (long long r = 0; r < c->N; ++r) sum += jh[k * c->N + r];
+            o->P[k] = a3 * sum;
+        }
     }
+    for (int k = 0; k < 3; ++k) o->v_cm[k] = o->N != 0.0 ? o->P[k] / o->N : 0.0;
     return LISE_OK;
 }
 
@@ -1894,6 +1979,7 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->eta));
     dfree(reinterpret_cast<void**>(&c->eta_part));
+    dfree(reinterpret_cast<void**>(&c->pz_part));
     for (int b = 0; b < 2; ++b) dfree(reinterpret_cast<void**>(&c->ez_part[b]));
     dfree(reinterpret_cast<void**>(&c->bad));
     dfree(reinterpret_cast<void**>(&c->dtime));

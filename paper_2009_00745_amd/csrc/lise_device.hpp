@@ -317,6 +317,10 @@ struct KPArgs {
     // per global qpwf: the instantaneous quasiparticle energy eta_j of
     // Eq. (sp_en), subtracted from H in every mode that applies H (null: off)
     const double* eta;
+    // KP_KINETIC on the register-FFT plane kernel, optional: per workgroup the
+    // Parseval sums over the v components of (m_x, m_y) |F_xy v|^2 (signed
+    // plane-wave indices, Nyquist index 0), for the total current
+    double* ppart;
 };
 
 // ---------------------------------------------------------------------------

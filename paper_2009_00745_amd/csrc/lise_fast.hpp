@@ -345,6 +345,43 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     for (int q = 0; q < P; ++q) st_hint<T, NT>(dst + (s + L * q) * a.nxy, x[q]);
 }
 
+// Total current along z by Parseval (Eq. j summed over the lattice): per
+// column of a v component, sum_kz m_z |F_z v|^2 with the signed plane-wave
+// index m_z (Nyquist index 0, as for every odd derivative), summed over the
+// workgroup's 256 columns in a fixed order.  One thread per column, the
+// column in registers; u columns contribute nothing.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(256) pz_kernel(const KZFastArgs<T> a, double* __restrict__ part) {
+    __shared__ cpx<T> tab[NZ];
+    __shared__ double red[256];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    __syncthreads();
+    const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (col < a.ncols) {
+        const long long jc = col / a.nxy, r = col - jc * a.nxy;
+        if ((int)(jc % a.C) >= a.nu) {
+            const cpx<T>* src = a.in + (a.j0 * a.C + jc) * NZ * a.nxy + r;
+            cpx<T> x[NZ];
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) x[z] = src[z * a.nxy];
+            RegFft<T, NZ, 1, false>::run(x, tab);
+#pragma unroll
+            for (int z = 0; z < NZ; ++z) {
+                const int m = (2 * z < NZ) ? z : (2 * z == NZ ? 0 : z - NZ);
+                e += double(m) * (double(x[z].re) * double(x[z].re) + double(x[z].im) * double(x[z].im));
+            }
+        }
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 // ---------------------------------------------------------------------------
 // xy planes of a square lattice side N; one workgroup per z-plane and group
 // of jg qpwfs; a row of the plane is spread over L lanes (lane s holds the
@@ -422,6 +459,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
 #pragma unroll
     for (int q = 0; q < PN; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
     double ekin = 0.0;
+    double pxs = 0.0, pys = 0.0;   // KP_KINETIC with a.ppart: total-current sums
     __syncthreads();
 
     for (int jl = jbeg; jl < jend; ++jl) {
@@ -485,6 +523,16 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
                         ekin += double(f) * (double(xa[k1].re) * double(xa[k1].re) + double(xa[k1].im) * double(xa[k1].im) -
                                              double(xb[k1].re) * double(xb[k1].re) - double(xb[k1].im) * double(xb[k1].im));
                     } else {
+                        if constexpr (MODE == KP_KINETIC) {
+                            // Parseval for the total current: sum_r Im(v^* d_x v) = sum_k k_x |F v|^2 / nxy
+                            // with the Nyquist index of the odd derivative zeroed
+                            if (a.ppart) {
+                                const double b2 = double(xb[k1].re) * double(xb[k1].re) +
+                                                  double(xb[k1].im) * double(xb[k1].im);
+                                pxs += (2 * mx == -N ? 0 : mx) * b2;
+                                pys += (2 * my == -N ? 0 : my) * b2;
+                            }
+                        }
                         xa[k1] = f * xa[k1];
                         xb[k1] = f * xb[k1];
                     }
@@ -576,15 +624,23 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     if constexpr (MODE == KP_ETAXY) return;
     if (MODE == KP_KINETIC || MODE == KP_ETA) {
         double* red = reinterpret_cast<double*>(smem_raw);
-        red[tid] = ekin;
-        __syncthreads();
-        int st = 1;
-        while (st < nth) st <<= 1;
-        for (st >>= 1; st > 0; st >>= 1) {
-            if (tid < st && tid + st < nth) red[tid] += red[tid + st];
+        const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const int nsum = (MODE == KP_KINETIC && a.ppart) ? 3 : 1;
+        for (int v = 0; v < nsum; ++v) {
+            red[tid] = v == 0 ? ekin : (v == 1 ? pxs : pys);
+            __syncthreads();
+            int st = 1;
+            while (st < nth) st <<= 1;
+            for (st >>= 1; st > 0; st >>= 1) {
+                if (tid < st && tid + st < nth) red[tid] += red[tid + st];
+                __syncthreads();
+            }
+            if (tid == 0) {
+                if (v == 0) a.epart[wg] = red[0];
+                else a.ppart[2 * wg + v - 1] = red[0];
+            }
             __syncthreads();
         }
-        if (tid == 0) a.epart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
         return;
     }
     if constexpr (NAT) {

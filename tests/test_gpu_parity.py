@@ -314,6 +314,40 @@ def test_current_density_matches_oracle(lise):
         assert e < tol and dP < 10 * tol
 
 
+def test_total_current_routes_agree(lise):
+    """The observables' total current P (Parseval sums of the kinetic pass and of a z pass
+    over the v components, register-FFT kernels) equals a^3 times the sum of the
+    current-density field, and both equal the oracle's, after a boost: FP64 16^3 (lane
+    order), 20^3 (natural order), C = 4 8^3, the generic kernels (field route only), FP32 24^3."""
+    cases = [(wl.config2(M=24, n=16), {}, 1e-11), (wl.config3(M=16, n=20, precision=wl.FP64), {}, 1e-11),
+             (wl.config4(M=24, n=8, precision=wl.FP64), {}, 1e-11),
+             (wl.config2(M=24, n=16), {"generic": 1}, 1e-11),
+             (wl.config3(M=16, n=24, precision=wl.FP32), {}, 1e-5)]
+    for w, tuning, tol in cases:
+        lat = w.lattice
+        p = np.array([2 * np.pi / (lat.nx * lat.a), -4 * np.pi / (lat.ny * lat.a), 2 * np.pi / (lat.nz * lat.a)])
+        chi = lattice_chi(lat, p, seed=5, amp=0.2)
+        say(f"total current {w.name} precision {w.functional.precision} tuning {tuning}: kick, 2 steps")
+        ctx = lise.Context(lat, w.M, w.functional)
+        if tuning:
+            ctx.set_tuning(**tuning)
+        ctx.set_qpwf(0, w.qpwfs())
+        ctx.kick(chi)
+        ctx.step(w.dt, 2)
+        obs = ctx.observables()
+        j = ctx.current()
+        psi = ctx.get_qpwf(0, w.M)
+        ctx.close()
+        P_field = lat.a ** 3 * j.reshape(3, -1).sum(axis=1)
+        P_ref = lat.a ** 3 * oracle.current_density(psi, lat, w.functional).reshape(3, -1).sum(axis=1)
+        scale = np.max(np.abs(P_ref))
+        d1 = float(np.max(np.abs(np.array(obs["P"]) - P_field)) / scale)
+        d2 = float(np.max(np.abs(np.array(obs["P"]) - P_ref)) / scale)
+        say(f"  P {obs['P']} field {P_field} oracle {P_ref}: rel diff {d1:.3e} / {d2:.3e}")
+        assert scale > 1e-3
+        assert d1 < tol and d2 < tol
+
+
 def test_kick_then_step_matches_oracle(lise):
     """Eq. (kick) with chi = p.r plus a smooth random field, then start-up + 10 ABM
     steps; C = 2 (16^3, FP64) and C = 4 (8^3, FP64)."""

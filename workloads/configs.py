@@ -247,7 +247,7 @@ def config3(seed=0, M=None, n=48, steps=1000, precision=FP32):
         out[:, 1] = (v * np.conj(eu)[None])[:, None] * pw
         out *= phase_noise(seed, 0, j, 2, lat.n, 1e-3).reshape(out.shape)
         return out
-    return Workload(f"cfg3_fp32_{n}c_m{M}", lat, fn, M, 0.002, steps, gen, seed,
+    return Workload(f"cfg3_{('fp64', 'fp32', 'mfma')[precision]}_{n}c_m{M}", lat, fn, M, 0.002, steps, gen, seed,
                     "LDA vortex Delta=0.4 tanh(rho/2) e^{i phi}, phase noise 1e-3")
 
 
