@@ -203,7 +203,7 @@ bool fast_side(int n) {
 
 size_t fast_kp_lds(const lise_ctx* c) {
     const size_t n = c->lat.nx;
-    const bool natural = !plane_stream_hint_of((int)c->esz / 2, (int)n);
+    const bool natural = plane_natural_of((int)c->esz / 2, (int)n);
     return (n + 2 * n * (n + 1) + (natural ? 2 * n * n : 0)) * c->esz;
 }
 
