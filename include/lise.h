@@ -127,7 +127,10 @@ typedef struct {
  *   mean_abs_delta = sum |Delta| n / sum n;  r_cm = sum r n / sum n;
  *   norm_drift_* = max / mean over j of |<psi_j|psi_j> - <psi_j|psi_j>_0|,
  *   relative to the norms when the qpwfs were last set;
- *   P = a^3 sum_r j(r) with j of lise_current, v_cm = P / N. */
+ *   P = a^3 sum_r j(r) with j of lise_current, v_cm = P / N.  With the
+ *   register-FFT kernels on all axes (square planes and sides of 8, 16, 20,
+ *   24, 32, 48 or 64) P is formed from Parseval sums of the same spectral
+ *   derivatives instead of the field (equal to rounding). */
 typedef struct {
     double t;
     int64_t step;
