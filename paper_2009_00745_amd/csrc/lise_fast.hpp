@@ -17,7 +17,11 @@
 //   restored.  Rows are transformed first, one LDS transpose gives columns,
 //   the k^2 multiply sits between the forward and inverse column transforms,
 //   and a second transpose returns rows for the inverse x transform, whose
-//   output feeds the local mixing and ABM epilogue straight from registers.
+//   output feeds the local mixing and ABM epilogue straight from registers
+//   (or, where L points of a row are less than a 128-byte line, through LDS
+//   in natural order: see kp_fast).
+//
+// pz_kernel: the z part of the total current by Parseval, for observables.
 #pragma once
 
 #include "lise_device.hpp"
