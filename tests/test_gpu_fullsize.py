@@ -43,8 +43,9 @@ def oracle_densities_chunked(w, piece=512):
 
 def test_config2_full_size(lise):
     w = wl.config2()
-    say(f"full size {w.name}: upload")
+    say(f"full size {w.name}: upload (launch shape of the benchmark's autotuned runs)")
     ctx = lise.Context(w.lattice, w.M, w.functional)
+    ctx.set_tuning(chunk_qpwf=2048, jgroup=8, no_overlap=1)
     upload(ctx, w)
     n, k = ctx.densities()
     n0, k0 = oracle_densities_chunked(w)
@@ -73,7 +74,7 @@ def test_config2_full_size(lise):
     ctx.close()
     say("  same evolution with another chunking")
     ctx2 = lise.Context(w.lattice, w.M, w.functional)
-    ctx2.set_tuning(chunk_qpwf=3000, jgroup=8, no_overlap=1)
+    ctx2.set_tuning(chunk_qpwf=3000, jgroup=32, no_overlap=0)
     upload(ctx2, w)
     ctx2.step(w.dt, 6)
     psi2 = ctx2.get_qpwf(0, 64)
