@@ -285,8 +285,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay four-step HIP graphs (kept by the autotuner)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-phase", action="store_true",
                     help="skip the variant with the trivial phase removed (Eq. sp_en)")
