@@ -143,8 +143,9 @@ typedef struct {
 } lise_obs;
 
 /* Launch tuning (0 = library default).
- *   chunk_qpwf : qpwfs per launch of the two apply-H kernels (bounds the
- *                scratch buffer and keeps it cache-resident)
+ *   chunk_qpwf : qpwfs per launch of the two apply-H kernels; sizes the
+ *                z-term scratch (chunk x C x N elements, a second one when
+ *                the z kernel overlaps; default: about 1 GiB of qpwfs)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
  *                (sets the number of density partial sums; default 32)
  *   fused      : whole-cube kernel (one pass, the cube in LDS): 1 = whenever
