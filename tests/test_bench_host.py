@@ -1,0 +1,56 @@
+"""Host-side checks of bench.py: the one-GPU rule, the CPU-baseline record, the
+workload table and the traffic record read from the committed profile."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_cpu_baseline_record():
+    import bench
+    rec = bench.cpu_baseline("cfg1", 2, 1)
+    assert set(rec) == {"value", "unit", "cores", "kind", "sample"}
+    assert rec["kind"] == "oracle" and rec["unit"] == "qpwf-steps/s"
+    assert rec["value"] > 0 and rec["cores"] >= 1
+    assert "2 of the workload's qpwfs" in rec["sample"]
+
+
+@pytest.mark.parametrize("name, shape, ncomp, prec", [
+    ("cfg1", (8, 8, 8), 2, 0), ("cfg2", (32, 32, 32), 2, 0), ("cfg2_fp32", (32, 32, 32), 2, 1),
+    ("cfg3", (48, 48, 48), 2, 1), ("cfg4", (64, 64, 64), 4, 2), ("cfg4_fp32", (64, 64, 64), 4, 1)])
+def test_workload_table(name, shape, ncomp, prec):
+    import bench
+    w = bench.make_workload(name, M=4)
+    lat = w.lattice
+    assert (lat.nx, lat.ny, lat.nz) == shape
+    assert w.functional.ncomp == ncomp and w.functional.precision == prec and w.M == 4
+
+
+def test_traffic_record_from_profile():
+    """The bench reads per-qpwf HBM bytes of the FP64 32^3 ABM kernels from the committed
+    PMC summary, or None when the kernel sources changed since the counters were taken."""
+    import bench
+    rec = bench.measured_traffic()
+    path = os.path.join(ROOT, "profiles", "kp_fast_fp64_32c_traffic.md")
+    line = [l for l in open(path) if l.startswith("TRAFFIC_JSON")][0]
+    stored = json.loads(line.split(" ", 1)[1])
+    for key in ("abm1_bytes_per_qpwf", "abm2_bytes_per_qpwf", "kz_bytes_per_qpwf"):
+        assert stored[key] > 0
+    # one 32^3 FP64 two-component state array per qpwf is 1 MiB: 10, 6 and 2 of them
+    mib = 1 << 20
+    assert 10 * mib <= stored["abm1_bytes_per_qpwf"] < 10.5 * mib
+    assert 6 * mib <= stored["abm2_bytes_per_qpwf"] < 6.5 * mib
+    assert 2 * mib <= stored["kz_bytes_per_qpwf"] < 2.05 * mib
+    assert rec is None or rec == stored
