@@ -1063,18 +1063,46 @@ int norms_t(lise_ctx* c, double* dst) {
     return check_launch(c, "norm_kernel");
 }
 
+template <typename T, int NS>
+void launch_jx_n(const CurArgs<T>& a, const cpx<T>* twN, int nslots, hipStream_t st) {
+    hipLaunchKernelGGL((jx_fast<T, NS>), dim3(a.nz, nslots), dim3(plane_block<T, NS>()), 0, st, a, twN);
+}
+
+template <typename T, int NA>
+void launch_jline_n(const CurArgs<T>& a, const cpx<T>* tw, int nslots, long long nlines, long long inner,
+                    long long outer, long long es, T f, int axis, hipStream_t st) {
+    dim3 grid((unsigned)((nlines + kJLineThreads - 1) / kJLineThreads), nslots);
+    hipLaunchKernelGGL((jline_fast<T, NA>), grid, dim3(kJLineThreads), 0, st, a, tw, nlines, inner, outer, es, f, axis);
+}
+
+// lines of a side n <= 32 along one axis (register FFTs)
+template <typename T>
+void launch_jline(const CurArgs<T>& a, int n, const cpx<T>* tw, int nslots, long long nlines, long long inner,
+                  long long outer, long long es, T f, int axis, hipStream_t st) {
+    switch (n) {
+        case 8: launch_jline_n<T, 8>(a, tw, nslots, nlines, inner, outer, es, f, axis, st); break;
+        case 16: launch_jline_n<T, 16>(a, tw, nslots, nlines, inner, outer, es, f, axis, st); break;
+        case 20: launch_jline_n<T, 20>(a, tw, nslots, nlines, inner, outer, es, f, axis, st); break;
+        case 24: launch_jline_n<T, 24>(a, tw, nslots, nlines, inner, outer, es, f, axis, st); break;
+        default: launch_jline_n<T, 32>(a, tw, nslots, nlines, inner, outer, es, f, axis, st); break;
+    }
+}
+
 // Current density of Eq. (j) of the current state into jdev (3N float64: x, y, z).
+// Register-FFT kernels where both plane and z kernels have them and the sides
+// are at most 32; LDS Stockham kernels otherwise.
 template <typename T>
 int current_t(lise_ctx* c, double* jdev) {
     const int nx = c->lat.nx, ny = c->lat.ny, nz = c->lat.nz;
     const long long nxy = (long long)nx * ny;
+    const bool fast = c->fast_xy && c->fast_z && nx <= 32 && nz <= 32;
     const int cap = c->prec == LISE_FP64 ? 2048 : 4096;
     int yb = 0;
     for (int d = ny; d >= 1; --d)
         if (ny % d == 0 && (long long)d * nx * nz <= cap) { yb = d; break; }
     const size_t lds_xy = 2 * (size_t)nxy * c->esz;
     const size_t lds_z = 2 * (size_t)nz * yb * nx * c->esz;
-    if (nxy > 16 * kThreads || yb == 0 || lds_xy > c->lds_limit || lds_z > c->lds_limit)
+    if (!fast && (nxy > 16 * kThreads || yb == 0 || lds_xy > c->lds_limit || lds_z > c->lds_limit))
         return fail(c, LISE_E_UNSUPPORTED, "current density: lattice %dx%dx%d too large for the LDS kernels", nx, ny, nz);
     CurArgs<T> a;
     std::memset(&a, 0, sizeof(a));
@@ -1100,17 +1128,36 @@ int current_t(lise_ctx* c, double* jdev) {
     a.jpart = c->dpart;
     const int nslots = (int)((c->M + c->jg - 1) / c->jg);
     if (nslots > c->slot_cap) return fail(c, LISE_E_STATE, "partial-sum buffer too small");
-    const long long pz = (long long)nz * yb * nx;
-    if (nxy <= 4 * kThreads)
-        hipLaunchKernelGGL((current_xy_kernel<T, 4>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
-    else
-        hipLaunchKernelGGL((current_xy_kernel<T, 16>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
-    CHK(check_launch(c, "current_xy_kernel"));
-    if (pz <= 4 * kThreads)
-        hipLaunchKernelGGL((current_z_kernel<T, 4>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
-    else
-        hipLaunchKernelGGL((current_z_kernel<T, 16>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
-    CHK(check_launch(c, "current_z_kernel"));
+    if (fast) {
+        const cpx<T>* twxy = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy;
+        const cpx<T>* twz = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
+        switch (nx) {
+            case 8: launch_jx_n<T, 8>(a, twxy, nslots, c->stream); break;
+            case 16: launch_jx_n<T, 16>(a, twxy, nslots, c->stream); break;
+            case 20: launch_jx_n<T, 20>(a, twxy, nslots, c->stream); break;
+            case 24: launch_jx_n<T, 24>(a, twxy, nslots, c->stream); break;
+            default: launch_jx_n<T, 32>(a, twxy, nslots, c->stream); break;
+        }
+        CHK(check_launch(c, "jx_fast"));
+        // y lines: line t = (z, x), points nx apart (nx == ny on this path)
+        launch_jline<T>(a, ny, twxy, nslots, (long long)nx * nz, nx, nxy, nx, a.fy, 1, c->stream);
+        CHK(check_launch(c, "jline_fast y"));
+        // z lines: line t = xy point, points nxy apart
+        launch_jline<T>(a, nz, twz, nslots, nxy, nxy, 0, nxy, a.fz, 2, c->stream);
+        CHK(check_launch(c, "jline_fast z"));
+    } else {
+        const long long pz = (long long)nz * yb * nx;
+        if (nxy <= 4 * kThreads)
+            hipLaunchKernelGGL((current_xy_kernel<T, 4>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
+        else
+            hipLaunchKernelGGL((current_xy_kernel<T, 16>), dim3(nz, nslots), dim3(kThreads), lds_xy, c->stream, a);
+        CHK(check_launch(c, "current_xy_kernel"));
+        if (pz <= 4 * kThreads)
+            hipLaunchKernelGGL((current_z_kernel<T, 4>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
+        else
+            hipLaunchKernelGGL((current_z_kernel<T, 16>), dim3(ny / yb, nslots), dim3(kThreads), lds_z, c->stream, a);
+        CHK(check_launch(c, "current_z_kernel"));
+    }
     const long long n3 = 3 * c->N;
     hipLaunchKernelGGL(slot_sum_kernel, dim3((unsigned)((n3 + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                        c->stream, c->dpart, nslots, n3, jdev);

@@ -387,6 +387,112 @@ __global__ void __launch_bounds__(256) pz_kernel(const KZFastArgs<T> a, double* 
 }
 
 // ---------------------------------------------------------------------------
+// Current density of Eq. (j) on the register-FFT path (sides up to 32):
+// j_a = -w sum_j sum_v Im(v^* d_a v), with the spectral first derivative along
+// one axis (1D forward transform, i k_a with the Nyquist index zeroed, 1D
+// inverse; the factor f carries 2 pi / L_a and the 1/n of the round trip).
+// Each thread accumulates over the qpwfs of its slot group (blockIdx.y) and
+// writes jpart[slot][axis][N]; a fixed-order slot sum follows.
+
+// x: the rows of an xy-plane over L lanes (the plane kernel's lane order), one
+// workgroup per z-plane and slot group.
+template <typename T, int N>
+__global__ void __launch_bounds__((plane_block<T, N>())) jx_fast(const CurArgs<T> a, const cpx<T>* __restrict__ twN) {
+    constexpr int L = plane_lanes<T, N>();
+    constexpr int P = N / L;
+    __shared__ cpx<T> tab[N];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N; i += blockDim.x) tab[i] = twN[i];
+    __syncthreads();
+    if (tid >= L * N) return;   // no barrier follows
+    const int row = tid / L, s = tid % L, brs = bitrev(s, L);
+    const int z = blockIdx.x;
+    constexpr long long nxy = (long long)N * N;
+    const long long N3 = nxy * a.nz;
+    const long long j0 = (long long)blockIdx.y * a.jg;
+    const long long j1 = min(a.M, j0 + a.jg);
+    double jx[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) jx[q] = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        for (int cv = 0; cv < a.nv; ++cv) {
+            const cpx<T>* src = a.in + ((j * a.C + a.v0 + cv) * a.nz + z) * nxy + row * N;
+            cpx<T> f[P], d[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                f[q] = src[s + L * q];
+                d[q] = f[q];
+            }
+            lane_fwd<T, P, L>(d, tab, s);
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) {
+                const T k = deriv_factor<T>(k1 + P * brs, N, a.fx);
+                d[k1] = mk(-k * d[k1].im, k * d[k1].re);   // i k F v
+            }
+            lane_inv<T, P, L>(d, tab, s);
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+                jx[q] -= a.w * (double(f[q].re) * double(d[q].im) - double(f[q].im) * double(d[q].re));
+        }
+    }
+    double* out = a.jpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy + row * N;
+#pragma unroll
+    for (int q = 0; q < P; ++q) out[s + L * q] = jx[q];
+}
+
+// y and z: one thread per line along the axis, the transformed line in
+// registers and its accumulators in LDS; consecutive threads take consecutive x (or xy
+// points), so each load of a wave is one contiguous run.  Line t starts at
+// (t / inner) * outer + t % inner; its NA points are es apart.
+constexpr int kJLineThreads = 128;
+template <typename T, int NA>
+__global__ void __launch_bounds__(kJLineThreads) jline_fast(const CurArgs<T> a, const cpx<T>* __restrict__ twA,
+                                                             long long nlines, long long inner, long long outer,
+                                                             long long es, T fa, int axis) {
+    __shared__ cpx<T> tab[NA];
+    __shared__ double acc[NA * kJLineThreads];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NA; i += blockDim.x) tab[i] = twA[i];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i * kJLineThreads + tid] = 0.0;
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * kJLineThreads + tid;
+    if (t >= nlines) return;   // no barrier follows
+    const long long base = (t / inner) * outer + t % inner;
+    const long long N3 = (long long)a.nx * a.ny * a.nz;
+    const long long j0 = (long long)blockIdx.y * a.jg;
+    const long long j1 = min(a.M, j0 + a.jg);
+#pragma unroll 1
+    for (long long j = j0; j < j1; ++j) {
+#pragma unroll 1
+        for (int cv = 0; cv < a.nv; ++cv) {
+            const cpx<T>* src = a.in + (j * a.C + a.v0 + cv) * N3 + base;
+            cpx<T> d[NA];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) d[i] = src[i * es];
+            RegFft<T, NA, 1, false>::run(d, tab);
+#pragma unroll
+            for (int m = 0; m < NA; ++m) {
+                const T k = deriv_factor<T>(m, NA, fa);
+                d[m] = mk(-k * d[m].im, k * d[m].re);
+            }
+            RegFft<T, NA, 1, true>::run(d, tab);
+            // v itself is read again (just fetched: a cache hit) instead of
+            // holding a second copy of the line in registers
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                const cpx<T> f = src[i * es];
+                acc[i * kJLineThreads + tid] -=
+                    a.w * (double(f.re) * double(d[i].im) - double(f.im) * double(d[i].re));
+            }
+        }
+    }
+    double* out = a.jpart + (long long)blockIdx.y * 3 * N3 + (long long)axis * N3 + base;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) out[i * es] = acc[i * kJLineThreads + tid];
+}
+
+// ---------------------------------------------------------------------------
 // xy planes of a square lattice side N; one workgroup per z-plane and group
 // of jg qpwfs; a row of the plane is spread over L lanes (lane s holds the
 // points s + L q).
