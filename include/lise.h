@@ -130,7 +130,11 @@ typedef struct {
  *   P = a^3 sum_r j(r) with j of lise_current, v_cm = P / N.  With the
  *   register-FFT kernels on all axes (square planes and sides of 8, 16, 20,
  *   24, 32, 48 or 64) P is formed from Parseval sums of the same spectral
- *   derivatives instead of the field (equal to rounding). */
+ *   derivatives instead of the field (equal to rounding).
+ *   N_up, N_dn: the spin-resolved terms of Eq. (rho_t), N_sigma = a^3 sum_r
+ *   sum_j |v_{j,sigma}|^2 (C = 4: components v_up, v_dn); the C = 2 reduction
+ *   is spin-symmetric by construction (each state of the (u_up, v_dn) block
+ *   stands for itself and its time-reversed partner), N_up = N_dn = N / 2. */
 typedef struct {
     double t;
     int64_t step;
@@ -140,6 +144,7 @@ typedef struct {
     double norm_drift_max, norm_drift_mean;
     double P[3];      /* a^3 sum_r j (total current of Eq. j) */
     double v_cm[3];   /* P / N (Eq. vel, m = hbar = 1) */
+    double N_up, N_dn;
 } lise_obs;
 
 /* Launch tuning (0 = library default).
@@ -180,8 +185,15 @@ int lise_init(lise_ctx **out, const lise_lattice *lat, int64_t n_qpwf,
 
 /* Copy qpwfs [first, first+count) from `src` (complex128, count*C*N
  * elements, layout above) into the state; `src_is_device` = 1 when src is a
- * device pointer.  Resets the time to t = 0 (or keeps t if already set, see
- * lise_set_time), discards the ABM history, and marks densities stale.
+ * device pointer.  Keeps the time (see lise_set_time), discards the ABM
+ * history, and marks densities stale.  The context records which qpwfs have
+ * been written: every call that needs the whole state (lise_step,
+ * lise_startup, lise_apply_h, lise_densities, lise_observables, lise_save,
+ * lise_kick, lise_current, lise_autotune, lise_batch_step) returns
+ * LISE_E_STATE until each of the M qpwfs has been covered by some call since
+ * the last reset.  Resets: context creation, a failed lise_load, and the
+ * first lise_set_qpwf after the state was evolved (the evolved qpwfs no
+ * longer sit where a partial update would leave them).
  * Errors: ARG, STATE, HIP. */
 int lise_set_qpwf(lise_ctx *c, int64_t first, int64_t count, const void *src, int32_t src_is_device);
 

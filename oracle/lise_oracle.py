@@ -444,6 +444,10 @@ def observables(psi, lat, fn, t):
       E_ext  = a^3 sum_r U_ext n.
     <|Delta|> = int |Delta| n / int n; r_cm = int r n / int n.
     P = int j (total current, Eq. j) and v_cm = P / N (Eq. vel with m = hbar = 1).
+    Spin-resolved numbers from the spin sum of Eq. (rho_t): N_sigma = int sum_k
+    |v_{k,sigma}|^2, i.e. the v_up and v_dn components for C = 4.  The C = 2
+    reduction is spin-symmetric by construction (each state of the (u_up, v_dn)
+    block stands for itself and its time-reversed partner): N_up = N_dn = N / 2.
     """
     a3 = lat.a ** 3
     n, kappa = densities(psi, fn)
@@ -466,8 +470,13 @@ def observables(psi, lat, fn, t):
            float(np.sum(n * xs[1][None, :, None])) / tot if tot else 0.0,
            float(np.sum(n * xs[2][:, None, None])) / tot if tot else 0.0]
     norms = a3 * np.sum(np.abs(psi) ** 2, axis=(1, 2, 3, 4))
+    if fn.ncomp == 4:
+        n_up = a3 * float(np.sum(np.abs(psi[:, 2]) ** 2))
+        n_dn = a3 * float(np.sum(np.abs(psi[:, 3]) ** 2))
+    else:
+        n_up = n_dn = 0.5 * N
     P = [a3 * float(np.sum(c)) for c in current_density(psi, lat, fn)]
-    return dict(t=t, N=N, E=ekin + e_int + e_pair + e_ext, E_kin=ekin, E_int=e_int,
+    return dict(t=t, N=N, N_up=n_up, N_dn=n_dn, E=ekin + e_int + e_pair + e_ext, E_kin=ekin, E_int=e_int,
                 E_pair=e_pair, E_ext=e_ext,
                 mean_abs_delta=float(np.sum(np.abs(Delta) * n)) / tot if tot else 0.0,
                 r_cm=rcm, norms=norms, P=P, v_cm=[p / N if N else 0.0 for p in P])

@@ -74,6 +74,8 @@ struct lise_ctx {
     double* V_tmp = nullptr;
     double* D_tmp = nullptr;
     void* tw = nullptr;
+    void* ah_buf = nullptr;    // staging of lise_apply_h (one piece, kept)
+    size_t ah_cap = 0;
     double* red = nullptr;     // reduction partials (observables)
     long long red_cap = 0;
     double* pz_part = nullptr;  // per-workgroup z-momentum sums (observables)
@@ -95,8 +97,8 @@ struct lise_ctx {
     int tw_full_xy = -1, tw_full_z = -1;    // offsets of W_n^j tables (j < n)
 
     // state
-    std::vector<char> set_mask;   // which qpwfs were set (coarse: count)
-    long long n_set = 0;
+    std::vector<unsigned char> set_mask;   // per qpwf: written since the last reset
+    long long n_set = 0;                   // qpwfs marked in set_mask
     bool dens_valid = false;
     double g_used = 0.0;       // coupling of Delta = -g kappa (bare or regularised)
     int remove_phase = 0;      // Eq. (sp_en): evolve with H - eta_j
@@ -915,53 +917,69 @@ int step_t(lise_ctx* c, double dt, long long nsteps) {
     return check_bad(c);
 }
 
+// H psi for qpwfs [first, first + count) in pieces of at most kApplyPiece
+// bytes of complex128 output: the plane kernel writes a piece (state
+// precision) into `stage`, which convert_kernel widens to complex128, straight
+// into `out` when it is device memory, else into `stage64` for a copy to the
+// host.  stage64 may equal stage in float64.  All buffers are indexed from the
+// piece's first qpwf.
+constexpr size_t kApplyPiece = 64u << 20;
+
+long long apply_piece_qpwfs(const lise_ctx* c) {
+    return std::max<long long>(1, (long long)(kApplyPiece / ((size_t)c->per * sizeof(cpx<double>))));
+}
+
 template <typename T>
-int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_is_device) {
+int apply_pieces_t(lise_ctx* c, long long first, long long count, long long piece, void* stage, void* stage64,
+                   void* out, int out_is_device) {
     CHK(ensure_fields_t<T>(c));
     CHK(launch_fields(c, 0, nullptr, c->dens_cur, c->V_cur, c->D_cur, 0.0));
-    // H psi into the p - c slot when there is no history, else a temporary
-    void* tmp = nullptr;
-    cpx<T>* dst;
-    const size_t nbytes = (size_t)count * c->per * c->esz;
-    if (c->hist) {
-        CHK(dalloc(c, &tmp, nbytes));
-        dst = reinterpret_cast<cpx<T>*>(tmp) - first * c->per;
-    } else {
-        dst = S<T>(c, 6);
-    }
-    KPArgs<T> a = kp_base<T>(c);
-    a.V = c->V_cur;
-    a.D = c->D_cur;
-    a.in = ycur<T>(c);
-    a.G = reinterpret_cast<const cpx<T>*>(c->G);
-    a.out = dst;
-    a.coef_re = 1.0;
-    a.coef_im = 0.0;
-    a.dens_src = 0;
-    int rc = apply_chunks<T, KP_APPLY>(c, a, first, count, 3);
-    if (rc == LISE_OK) {
-        const cpx<T>* src = dst + first * c->per;
-        const long long n = count * c->per;
-        void* d64 = out;
-        void* stage = nullptr;
+    for (long long j0 = first; j0 < first + count; j0 += piece) {
+        const long long k = std::min<long long>(piece, first + count - j0);
+        cpx<T>* st = reinterpret_cast<cpx<T>*>(stage);
+        KPArgs<T> a = kp_base<T>(c);
+        a.V = c->V_cur;
+        a.D = c->D_cur;
+        a.in = ycur<T>(c);
+        a.G = reinterpret_cast<const cpx<T>*>(c->G);
+        a.out = st - j0 * c->per;     // the kernel indexes out by the global qpwf
+        a.coef_re = 1.0;
+        a.coef_im = 0.0;
+        a.dens_src = 0;
+        CHK((apply_chunks<T, KP_APPLY>(c, a, j0, k, 3)));
+        const long long n = k * c->per;
+        cpx<double>* dst = out_is_device ? reinterpret_cast<cpx<double>*>(out) + (j0 - first) * c->per
+                                         : reinterpret_cast<cpx<double>*>(stage64);
+        if (out_is_device || (void*)dst != (void*)st) {
+            hipLaunchKernelGGL((convert_kernel<double, T>), dim3(2048), dim3(kThreads), 0, c->stream, st, dst, n);
+            CHK(check_launch(c, "convert_kernel"));
+        }
         if (!out_is_device) {
-            rc = dalloc(c, &stage, (size_t)n * sizeof(cpx<double>));
-            d64 = stage;
+            HIPCHK(c, hipMemcpyAsync(reinterpret_cast<cpx<double>*>(out) + (j0 - first) * c->per, dst,
+                                     (size_t)n * sizeof(cpx<double>), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));   // stage64 is reused by the next piece
         }
-        if (rc == LISE_OK) {
-            hipLaunchKernelGGL((convert_kernel<double, T>), dim3(2048), dim3(kThreads), 0, c->stream, src,
-                               reinterpret_cast<cpx<double>*>(d64), n);
-            rc = check_launch(c, "convert_kernel");
-        }
-        if (rc == LISE_OK && !out_is_device) {
-            hipError_t e = hipMemcpyAsync(out, stage, (size_t)n * sizeof(cpx<double>), hipMemcpyDeviceToHost, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            if (e != hipSuccess) rc = fail(c, LISE_E_HIP, "copy of H psi failed: %s", hipGetErrorString(e));
-        }
-        if (stage) { (void)hipStreamSynchronize(c->stream); dfree(&stage); }
     }
-    if (tmp) { (void)hipStreamSynchronize(c->stream); dfree(&tmp); }
-    return rc;
+    return LISE_OK;
+}
+
+// lise_apply_h: a context-owned staging buffer of one piece (allocated at the
+// first call and kept), so that no call allocates more than one piece and
+// later calls allocate nothing.
+template <typename T>
+int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_is_device) {
+    const long long piece = apply_piece_qpwfs(c);
+    const size_t st_bytes = (size_t)piece * c->per * c->esz;
+    const size_t need = st_bytes + (sizeof(T) == 8 ? 0 : (size_t)piece * c->per * sizeof(cpx<double>));
+    if (c->ah_cap < need) {
+        dfree(&c->ah_buf);
+        c->ah_cap = 0;
+        CHK(dalloc(c, &c->ah_buf, need));
+        c->ah_cap = need;
+    }
+    void* stage = c->ah_buf;
+    void* stage64 = sizeof(T) == 8 ? stage : static_cast<char*>(c->ah_buf) + st_bytes;
+    return apply_pieces_t<T>(c, first, count, piece, stage, stage64, out, out_is_device);
 }
 
 // Kinetic energy of the current state (plane kernel in mode KP_KINETIC).  With
@@ -1229,6 +1247,34 @@ int observables_t(lise_ctx* c, lise_obs* o) {
     }
     o->norm_drift_max = mx;
     o->norm_drift_mean = c->M ? mean / c->M : 0.0;
+    // spin-resolved numbers (Eq. rho_t): C = 4 sums |v_up|^2 and |v_dn|^2 per
+    // qpwf; the C = 2 reduction is spin-symmetric
+    if (c->C == 4) {
+        double* part = c->dens_tmp;   // 2M doubles of scratch between steps
+        if (2 * c->M > 3 * c->N) {
+            if (c->red_cap < 2 * c->M) {
+                dfree(reinterpret_cast<void**>(&c->red));
+                CHK(dalloc(c, reinterpret_cast<void**>(&c->red), (size_t)(2 * c->M) * sizeof(double)));
+                c->red_cap = 2 * c->M;
+            }
+            part = c->red;
+        }
+        hipLaunchKernelGGL((comp_norm_kernel<T>), dim3((unsigned)(2 * c->M)), dim3(kThreads), 0, c->stream, ycur<T>(c),
+                           c->C, 2, 2, c->N, part);
+        CHK(check_launch(c, "comp_norm_kernel"));
+        std::vector<double> hs(2 * c->M);
+        HIPCHK(c, hipMemcpyAsync(hs.data(), part, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        double up = 0.0, dn = 0.0;
+        for (long long j = 0; j < c->M; ++j) {
+            up += hs[2 * j];
+            dn += hs[2 * j + 1];
+        }
+        o->N_up = a3 * up;
+        o->N_dn = a3 * dn;
+    } else {
+        o->N_up = o->N_dn = 0.5 * o->N;
+    }
     // total current and centre-of-mass velocity (Eq. j, Eq. vel with m = hbar = 1)
     if (parseval_p) {
         // sum_r Im(v^* d_a v) = (2 pi / L_a) sum_k m_a |F v|^2 / (transform size):
@@ -1256,6 +1302,12 @@ int observables_t(lise_ctx* c, lise_obs* o) {
     }
     for (int k = 0; k < 3; ++k) o->v_cm[k] = o->N != 0.0 ? o->P[k] / o->N : 0.0;
     return LISE_OK;
+}
+
+// Forget which qpwfs were written (they must all be set again).
+void reset_coverage(lise_ctx* c) {
+    std::fill(c->set_mask.begin(), c->set_mask.end(), (unsigned char)0);
+    c->n_set = 0;
 }
 
 int valid_dim(int n) {
@@ -1411,6 +1463,11 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     c->prec = fn->precision == LISE_FP64 ? LISE_FP64 : LISE_FP32;
     c->esz = c->prec == LISE_FP64 ? 16 : 8;
     c->M = n_qpwf;
+    try {
+        c->set_mask.assign((size_t)n_qpwf, 0);
+    } catch (...) {
+        return bail(fail(c, LISE_E_NOMEM, "host allocation of the qpwf coverage map failed"));
+    }
     c->N = (long long)lat->nx * lat->ny * lat->nz;
     c->per = (long long)c->C * c->N;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1493,10 +1550,10 @@ int lise_set_qpwf(lise_ctx* c, int64_t first, int64_t count, const void* src, in
     const long long n = count * c->per;
     void* dst = static_cast<char*>(c->buf[0]) + (size_t)first * c->per * c->esz;
     if (c->hist || c->iy != 0) {
-        // a previous evolution moved y_n away from buffer 0: start over there,
-        // and require the whole set again
+        // a previous evolution moved y_n away from buffer 0 (or left history
+        // behind it): start over there, and require the whole set again
         c->iy = 0;
-        c->n_set = 0;
+        reset_coverage(c);
     }
     if (c->prec == LISE_FP64) {
         HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)n * 16, src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -1525,7 +1582,11 @@ int lise_set_qpwf(lise_ctx* c, int64_t first, int64_t count, const void* src, in
         CHK(check_launch(c, "convert_kernel"));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->n_set = std::min<long long>(c->M, std::max<long long>(c->n_set, first + count));
+    for (long long j = first; j < first + count; ++j)
+        if (!c->set_mask[j]) {
+            c->set_mask[j] = 1;
+            ++c->n_set;
+        }
     c->hist = false;
     c->dens_valid = false;
     if (c->n_set >= c->M) {
@@ -1689,6 +1750,7 @@ int lise_memory(const lise_ctx* c, int64_t* bytes) {
     b += (c->Gbuf[1] ? 2 : 1) * c->g_cap * c->per * (long long)c->esz;
     b += (long long)c->slot_cap * 3 * c->N * 8;
     b += 10LL * c->N * 8;
+    b += (long long)c->ah_cap;
     *bytes = b;
     return LISE_OK;
 }
@@ -1767,13 +1829,14 @@ int lise_load(lise_ctx* c, const char* path) {
     fclose(f);
     if (rc != LISE_OK) {
         // the state may be partly overwritten: require a fresh set
-        c->n_set = 0;
+        reset_coverage(c);
         c->hist = false;
         c->dens_valid = false;
         return rc;
     }
     c->iy = 0;
     c->dn = 0;
+    std::fill(c->set_mask.begin(), c->set_mask.end(), (unsigned char)1);
     c->n_set = c->M;
     c->norms0_valid = true;
     c->t = h.t;
@@ -2022,6 +2085,7 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->D_tmp));
     dfree(&c->tw);
     dfree(reinterpret_cast<void**>(&c->red));
+    dfree(&c->ah_buf);
     dfree(reinterpret_cast<void**>(&c->norms));
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->eta));

@@ -1047,6 +1047,31 @@ __global__ void __launch_bounds__(256) norm_kernel(const cpx<T>* __restrict__ in
     if (threadIdx.x == 0) norms[j] = red[0];
 }
 
+// Squared norm of one component of each qpwf, sum over points of |psi_c|^2
+// (float64): workgroup b takes component c = cbeg + b % ncomp_sum of qpwf
+// j = b / ncomp_sum and writes out[b] (spin-resolved particle numbers).
+template <typename T>
+__global__ void __launch_bounds__(256) comp_norm_kernel(const cpx<T>* __restrict__ in, int C, int cbeg, int nc,
+                                                        long long N, double* __restrict__ out) {
+    __shared__ double red[256];
+    const long long b = blockIdx.x;
+    const long long j = b / nc;
+    const int c = cbeg + (int)(b % nc);
+    const cpx<T>* p = in + (j * C + c) * N;
+    double s = 0.0;
+    for (long long e = threadIdx.x; e < N; e += blockDim.x) {
+        const double re = double(p[e].re), im = double(p[e].im);
+        s += re * re + im * im;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = red[0];
+}
+
 // Precision conversion between the float64 interface and the state.
 template <typename TO, typename TI>
 __global__ void __launch_bounds__(256) convert_kernel(const cpx<TI>* __restrict__ in, cpx<TO>* __restrict__ out,

@@ -48,7 +48,8 @@ class Obs(ct.Structure):
                 ("E_int", ct.c_double), ("E_pair", ct.c_double), ("E_ext", ct.c_double),
                 ("mean_abs_delta", ct.c_double), ("r_cm", ct.c_double * 3),
                 ("norm_drift_max", ct.c_double), ("norm_drift_mean", ct.c_double),
-                ("P", ct.c_double * 3), ("v_cm", ct.c_double * 3)]
+                ("P", ct.c_double * 3), ("v_cm", ct.c_double * 3),
+                ("N_up", ct.c_double), ("N_dn", ct.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

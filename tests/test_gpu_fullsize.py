@@ -67,9 +67,29 @@ def test_config2_full_size(lise):
     say(f"  norm drift {o1['norm_drift_max']:.2e}, dN {o1['N'] - o0['N']:.2e}")
     assert o1["norm_drift_max"] < 1e-11
     assert abs(o1["N"] - o0["N"]) < 1e-9 * o0["N"]
-    # sampled step check: one more step of the GPU state against the oracle's apply-H
-    # of the same sampled qpwfs is covered by the reduced-size step tests; here the
-    # GPU step must also agree with a second GPU run in a different launch shape
+    # the evolved full-size state against the oracle: its densities, recomputed by the
+    # oracle from the state the GPU returns, equal lise_densities; H psi of sampled
+    # qpwfs under the oracle's fields of that state at the current time equals
+    # lise_apply_h
+    t_now, _ = ctx.time()
+    n1, k1 = ctx.densities()
+    nr = np.zeros_like(n1)
+    kr = np.zeros_like(k1)
+    for j0 in range(0, w.M, 512):
+        dn, dk = oracle.densities(ctx.get_qpwf(j0, min(512, w.M - j0)), w.functional)
+        nr += dn
+        kr += dk
+    en, ek = np.max(np.abs(n1 - nr)) / np.max(np.abs(nr)), np.max(np.abs(k1 - kr)) / np.max(np.abs(kr))
+    say(f"  evolved state: densities rel max err n {en:.2e} kappa {ek:.2e}")
+    assert en < 1e-13 and ek < 1e-13
+    V1, D1 = oracle.potentials(nr, kr, w.lattice, w.functional, t_now)
+    for j in (0, 5, 2049, 6000, w.M - 1):
+        got = ctx.apply_h(j, 1)
+        ref = oracle.apply_h(ctx.get_qpwf(j, 1), V1, D1, w.lattice, w.functional)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        say(f"  evolved apply_h qpwf {j}: rel max err {err:.2e}")
+        assert err < 1e-12
+    # and the GPU step must agree with a second GPU run in a different launch shape
     psi = ctx.get_qpwf(0, 64)
     ctx.close()
     say("  same evolution with another chunking")

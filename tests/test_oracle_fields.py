@@ -133,3 +133,57 @@ def test_energy_flow_with_four_components():
     o = oracle.observables(psi, lat, fn, 0.0)
     assert abs(ddt("E", psi, lat, fn)) < 1e-8 * o["E_kin"]
     assert abs(ddt("E_pair", psi, lat, fn)) > 1e-4 * abs(o["E_pair"])
+
+
+def test_spin_resolved_numbers_closed_form():
+    """N_up, N_dn of the spin sum of Eq. (rho_t) on a spin-imbalanced C = 4 BCS set.
+
+    Block A states carry (u_up, v_dn) = (u_k, v_k) e^{ik.r}/sqrt(V), block B states
+    (u_dn, v_up) = (u_k, -v_k) e^{ik.r}/sqrt(V); with na != nb the two spin numbers
+    differ, so a swapped or dropped component fails: N_dn = sum_A v_k^2,
+    N_up = sum_B v_k^2, N = N_up + N_dn.  The C = 2 reduction is spin-symmetric."""
+    lat = wl.Lattice(4, 4, 6, 0.9)
+    N3 = lat.n
+    fn = wl.Functional(ncomp=4, mu_up=0.6, mu_dn=0.4, beta=0.37, g=2.0, w=1.0)
+    na, nb = 11, 5
+    kx = 2 * np.pi * np.fft.fftfreq(4, d=lat.a)
+    kz = 2 * np.pi * np.fft.fftfreq(6, d=lat.a)
+    ks = sorted(((a, b, c) for a in kx for b in kx for c in kz), key=lambda k: (k[0] ** 2 + k[1] ** 2 + k[2] ** 2, k))
+    z, y, x = np.meshgrid(np.arange(6) * lat.a, np.arange(4) * lat.a, np.arange(4) * lat.a, indexing="ij")
+    vol = N3 * lat.a ** 3
+    psi = np.zeros((na + nb, 4, 6, 4, 4), dtype=complex)
+    vsq = []
+    for j in range(na + nb):
+        k = ks[j if j < na else j - na]
+        xi = 0.5 * (k[0] ** 2 + k[1] ** 2 + k[2] ** 2) - 0.5
+        E = math.sqrt(xi * xi + 0.25 ** 2)
+        u, v = math.sqrt(0.5 * (1 + xi / E)), math.sqrt(0.5 * (1 - xi / E))
+        pw = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)) / math.sqrt(vol)
+        if j < na:
+            psi[j, 0], psi[j, 3] = u * pw, v * pw
+        else:
+            psi[j, 1], psi[j, 2] = u * pw, -v * pw
+        vsq.append(v * v)
+    o = oracle.observables(psi, lat, fn, 0.0)
+    assert abs(o["N_dn"] - sum(vsq[:na])) < 1e-13
+    assert abs(o["N_up"] - sum(vsq[na:])) < 1e-13
+    assert abs(o["N"] - o["N_up"] - o["N_dn"]) < 1e-13
+    assert abs(o["N_dn"] - o["N_up"]) > 0.01
+    # C = 2: spin-symmetric halves
+    f2 = wl.Functional(ncomp=2, mu_up=0.5, mu_dn=0.5, beta=0.37, g=2.0, w=2.0)
+    p2 = psi[:na][:, [0, 3]]
+    o2 = oracle.observables(p2, lat, f2, 0.0)
+    assert o2["N_up"] == o2["N_dn"] == 0.5 * o2["N"]
+    assert abs(o2["N"] - 2 * sum(vsq[:na])) < 1e-13
+
+
+def test_spin_numbers_constant_along_exact_flow():
+    """dN_up/dt = dN_dn/dt = 0 along f = -i H psi for a complete C = 4 quasiparticle
+    vacuum whose chemical potentials differ enough to leave one unpaired spin-up
+    state: the vacuum then holds exactly one more up than down particle."""
+    lat = wl.Lattice(4, 4, 4, 1.0)
+    fn = wl.Functional(ncomp=4, mu_up=1.2, mu_dn=0.2, beta=0.37, g=1.5, w=1.0)
+    psi = bdg_vacuum(lat, fn, 7, ncomp=4)
+    o = oracle.observables(psi, lat, fn, 0.0)
+    assert abs(o["N_up"] - o["N_dn"] - 1.0) < 1e-12
+    assert abs(ddt("N_up", psi, lat, fn)) < 1e-9 and abs(ddt("N_dn", psi, lat, fn)) < 1e-9
