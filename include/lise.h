@@ -245,8 +245,9 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
  * lise_profile(c, 1) starts recording an event pair around every launch of
  * the library's kernels; lise_profile(c, 0) stops.  lise_profile_read
  * synchronises, then returns for kernel class `which` (0 = plane kernel of
- * the ABM phases, 1 = z-axis kernel, 2 = density reduction + potentials,
- * 3 = plane kernel outside the ABM phases: start-up, apply-H, energy) the
+ * ABM phase 1, 1 = z-axis kernel, 2 = density reduction + potentials,
+ * 3 = plane kernel outside the ABM phases: start-up, apply-H, energy,
+ * 4 = plane kernel of ABM phase 2) the
  * number of launches and their summed duration in milliseconds, and clears
  * that class's counters.  Returns LISE_E_STATE if more than 8192 launches
  * were recorded since the previous read (the event pool is fixed). */
@@ -314,22 +315,50 @@ int lise_current(lise_ctx *c, double *j_out, int32_t out_is_device);
 int lise_coupling(const lise_lattice *lat, const lise_functional *fn, double *g_out);
 
 /* Batch of independent systems (for example different lattices and qpwf
- * counts) advanced together.  lise_batch_create takes nsys distinct contexts
- * on the current device and moves all of them onto `hip_stream`; the
- * contexts stay owned by the caller and usable (densities, observables) but
- * must not be freed before the batch.  lise_batch_step forks one internal
- * stream per system from `hip_stream`, advances every system by nsteps ABM
- * steps on its own stream (start-up first if needed; with graphs enabled in
- * the system's tuning, its four-step graph replays as in lise_step), joins
- * the streams back into `hip_stream` and returns after all systems finished.
- * The systems' kernels run concurrently on the device, as far as the
- * process's HIP hardware queues allow (GPU_MAX_HW_QUEUES, 4 by default, read
- * when HIP initialises; 16 measured 1.14-1.23x faster for 16-64 systems).
- * Results equal lise_step on each system alone, bit for bit.
- * Errors: ARG, STATE, HIP, NAN (text from lise_batch_last_error). */
+ * counts) advanced together by the ABM step of Eq. (p), (m), (c), (y), each
+ * under its own Eq. (tdslda) and densities (Sec. "Time evolution"; the batched
+ * transforms of Sec. "FFT in batch").  lise_batch_create takes nsys distinct
+ * contexts on the current device and moves all of them onto `hip_stream`;
+ * the contexts stay owned by the caller and usable (densities, observables)
+ * but must not be freed before the batch, nor stepped on their own while the
+ * batch is in use (lise_batch_step notices and rebuilds its tables).
+ *
+ * lise_batch_step advances every system by nsteps ABM steps (start-up first
+ * where a system has no history for dt).  Systems whose lattice the
+ * register-FFT kernels cover (square xy-planes and z of side 8, 16, 20, 24,
+ * 32, 48 or 64; LISE_FP64 or LISE_FP32; no phase removal; default kernels)
+ * form groups of equal precision, xy side and z side.  Per ABM phase each
+ * group runs one z-axis launch and one plane-kernel launch over all qpwfs of
+ * all its systems (a device table holds one descriptor per system: buffers,
+ * fields, functional, qpwf count and jgroup), then one launch rebuilds the
+ * densities and fields of every grouped system and one more advances their
+ * times.  With graphs on (the default) four steps, one period of the buffer
+ * ring, are captured once on an internal stream as one graph of kernel
+ * nodes and replayed on `hip_stream`; steps that do not fill a period run
+ * eagerly.  The group's z-term scratch (sum over its systems of M*C*N
+ * elements) is allocated by the first step.  Other systems are stepped one
+ * after another on the same stream.  Results equal lise_step on each system
+ * alone bit for bit when that system's chunk_qpwf covers all its qpwfs (the
+ * default for up to about 1 GiB of qpwfs), since the density sums then run
+ * in the same order.  Returns after all systems finished.
+ * Errors: ARG, STATE, UNSUPPORTED (a group with more plane-kernel workgroup
+ * rows than the device's grid allows), NOMEM, HIP, NAN (text from
+ * lise_batch_last_error).
+ *
+ * lise_batch_set_graph: 1 (default) = replay captured periods, 0 = eager.
+ * lise_batch_info: number of groups and of systems stepped one by one, as
+ * of the last lise_batch_step (0, 0 before the first).
+ * lise_batch_profile / lise_batch_profile_read: HIP-event timing of the
+ * batch's launches, as lise_profile, for kernel class `which` (0 = plane
+ * kernel of ABM phase 1, 1 = z-axis kernel, 2 = densities + fields, 3 =
+ * plane kernel of ABM phase 2); steps run eagerly while profiling is on. */
 typedef struct lise_batch lise_batch;
 int lise_batch_create(lise_batch **out, int32_t nsys, lise_ctx *const *ctxs, void *hip_stream);
 int lise_batch_step(lise_batch *b, double dt, int64_t nsteps);
+int lise_batch_set_graph(lise_batch *b, int32_t enable);
+int lise_batch_info(const lise_batch *b, int32_t *ngroups, int32_t *nsolo);
+int lise_batch_profile(lise_batch *b, int32_t enable);
+int lise_batch_profile_read(lise_batch *b, int32_t which, int64_t *launches, double *total_ms);
 const char *lise_batch_last_error(const lise_batch *b);
 void lise_batch_free(lise_batch *b);
 

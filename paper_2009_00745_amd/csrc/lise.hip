@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kThreads = 256;
 const char* kVersion = "lise-mi355x 0.1 (gfx950)";
+constexpr int kBatchPeriod = 4;   // ABM steps after which the buffer ring repeats
 
 struct Prof {
     bool on = false;
@@ -36,8 +37,8 @@ struct Prof {
     size_t used = 0;
     struct Rec { int cls; hipEvent_t a, b; };
     std::vector<Rec> recs;
-    double total_ms[4] = {0, 0, 0, 0};
-    long long count[4] = {0, 0, 0, 0};
+    double total_ms[5] = {0, 0, 0, 0, 0};
+    long long count[5] = {0, 0, 0, 0, 0};
     bool overflow = false;
 };
 
@@ -233,6 +234,8 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 template <typename T>
@@ -806,7 +809,7 @@ int abm_step_t(lise_ctx* c) {
         a.a5 = S<T>(c, 6);                          // p_n - c_n -> p_{n+1} - c_{n+1}
         a.dt = dt;
         a.dens_src = 1;
-        CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 0, 1)));
+        CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 4, 1)));
     }
     CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, dt));
     CHK(tick(c, dt));
@@ -845,6 +848,7 @@ int abm_step_any(lise_ctx* c) { return c->prec == LISE_FP64 ? abm_step_t<double>
 // be capturing).  The ring of buffers returns to its state after kPeriod
 // steps, so the captured work can be replayed.  Host bookkeeping is restored.
 constexpr int kPeriod = 4;
+static_assert(kPeriod == kBatchPeriod, "the batch replays the same ring period");
 int capture_period(lise_ctx* c) {
     const HostState h = save_host(c);
     c->capturing = true;
@@ -1320,16 +1324,50 @@ int valid_dim(int n) {
 
 }  // namespace
 
-// A batch of independent systems advanced together.  Each system runs on a
-// stream of its own (forked from the caller's stream and joined back), so
-// the systems' kernels overlap on the device; within a system the usual
-// four-step graph replays apply.
+// A batch of independent systems advanced together.  Systems whose lattice
+// the register-FFT kernels cover are grouped by (precision, xy side, z side);
+// per ABM phase each group runs ONE z-axis launch and ONE plane-kernel launch
+// over all qpwfs of all its systems, driven by device tables with one
+// descriptor per system (its buffers, fields, functional, qpwf count).  One
+// launch reduces the densities and forms the fields of every system, one more
+// advances every system's time.  Four steps (one period of the buffer ring)
+// are captured once, on a single internal stream, as one graph holding only
+// kernel nodes, and replayed.  Other systems step one after another on the
+// batch stream.
+struct BatchGroup {
+    int prec = LISE_FP64;
+    int nx = 0, nz = 0;
+    std::vector<int> sys;          // indices into lise_batch::sys
+    std::vector<size_t> goff;      // byte offset of each system's region of the z-scratch
+    size_t gbytes = 0;             // z-scratch of the group: sum of M * C * N elements
+    long long qpwfs = 0;           // sum of M over the group
+    int rows = 0;                  // plane-kernel workgroup rows (sum of ceil(M / jg))
+    long long zblocks = 0;         // z-kernel workgroups
+    size_t off_rows = 0, off_blks = 0;   // device table offsets (bytes)
+    size_t off_kp[kBatchPeriod][2] = {}, off_kz[kBatchPeriod][2] = {};
+};
+
 struct lise_batch {
     std::vector<lise_ctx*> sys;
     hipStream_t stream = nullptr;   // caller's stream (may be the null stream)
-    std::vector<hipStream_t> fork;
-    hipEvent_t ev_fork = nullptr;
-    std::vector<hipEvent_t> ev_join;
+    hipStream_t cap = nullptr;      // internal stream the graph is captured on
+    hipEvent_t ev_cap = nullptr;
+    std::vector<BatchGroup> groups;
+    std::vector<int> grouped, solo;   // systems in a group / stepped one by one
+    void* G = nullptr;               // z-scratch of the largest group
+    size_t g_bytes = 0;
+    void* dtab = nullptr;            // descriptor tables
+    size_t dtab_bytes = 0;
+    size_t off_fblks = 0, off_fd[2] = {0, 0}, off_tick = 0;
+    long long fblocks = 0;
+    bool tables = false;
+    double tab_dt = 0.0;
+    int tphase = 0;                  // steps taken since the tables' base ring state
+    std::vector<int> base_iy, base_dn;
+    std::vector<long long> base_cfg;
+    int use_graph = 1;
+    hipGraphExec_t gexec = nullptr;
+    Prof prof;
     char err[512] = {0};
 };
 
@@ -1341,6 +1379,402 @@ int bfail(lise_batch* b, int code, const char* fmt, ...) {
     vsnprintf(b->err, sizeof(b->err), fmt, ap);
     va_end(ap);
     return code;
+}
+
+#define BCHK(call)                 \
+    do {                           \
+        int rc_ = (call);          \
+        if (rc_ != LISE_OK) return rc_; \
+    } while (0)
+
+int bcheck_launch(lise_batch* b, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return LISE_OK;
+}
+
+// per-class event pairs around the batch's launches (0 plane kernel of phase 1,
+// 1 z axis, 2 fields, 3 plane kernel of phase 2)
+void bprof_begin(lise_batch* b, hipEvent_t* ev, hipStream_t st) {
+    *ev = nullptr;
+    if (!b->prof.on) return;
+    if (b->prof.used + 2 > b->prof.pool.size()) {
+        b->prof.overflow = true;
+        return;
+    }
+    *ev = b->prof.pool[b->prof.used];
+    (void)hipEventRecord(*ev, st);
+}
+void bprof_end(lise_batch* b, int cls, hipEvent_t a, hipStream_t st) {
+    if (!a) return;
+    hipEvent_t e = b->prof.pool[b->prof.used + 1];
+    b->prof.used += 2;
+    (void)hipEventRecord(e, st);
+    b->prof.recs.push_back({cls, a, e});
+}
+
+// A system joins a group when both register-FFT kernels cover its lattice and
+// no per-qpwf pass (phase removal) or other plane kernel is in use.
+bool batch_groupable(const lise_ctx* c) {
+    return c->fast_xy && c->fast_z && !c->mfma_xy && !c->fused && !c->remove_phase && !c->generic;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Ring state of system c after `step` steps from the tables' base state.
+void batch_ring(const lise_batch* b, int i, int step, int* iy, int* dn) {
+    *iy = b->base_iy[i] ^ (step & 1);
+    *dn = (b->base_dn[i] + step) % 4;
+}
+
+template <typename T>
+void batch_fill_group(lise_batch* b, const BatchGroup& g, std::vector<unsigned char>& h, double dt) {
+    const int ns = (int)g.sys.size();
+    std::vector<int> rows(ns + 1, 0);
+    std::vector<long long> blks(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) {
+        const lise_ctx* c = b->sys[g.sys[i]];
+        rows[i + 1] = rows[i] + (int)((c->M + c->jg - 1) / c->jg);
+        const long long ncols = c->M * c->C * (long long)c->lat.nx * c->lat.ny;
+        blks[i + 1] = blks[i] + (ncols * kz_lanes_of(c->lat.nz) + kThreads - 1) / kThreads;
+    }
+    std::memcpy(h.data() + g.off_rows, rows.data(), rows.size() * sizeof(int));
+    std::memcpy(h.data() + g.off_blks, blks.data(), blks.size() * sizeof(long long));
+    for (int st = 0; st < kBatchPeriod; ++st)
+        for (int ph = 0; ph < 2; ++ph)
+            for (int i = 0; i < ns; ++i) {
+                lise_ctx* c = b->sys[g.sys[i]];
+                int iy, dn;
+                batch_ring(b, g.sys[i], st, &iy, &dn);
+                const int d0 = 2 + dn, d1 = 2 + (dn + 3) % 4, d2 = 2 + (dn + 2) % 4, d3 = 2 + (dn + 1) % 4;
+                const int yn = iy, ym1 = 1 - iy;
+                cpx<T>* Gs = reinterpret_cast<cpx<T>*>(static_cast<char*>(b->G) + g.goff[i]);
+                KPArgs<T> a = kp_base<T>(c);
+                a.j0 = 0;
+                a.kcount = (int)c->M;
+                a.G = Gs;
+                a.dt = dt;
+                a.dens_src = 1;
+                a.accumulate = 0;
+                a.eta = nullptr;
+                if (ph == 0) {   // as abm_step_t, phase 1
+                    a.V = c->V_cur;
+                    a.D = c->D_cur;
+                    a.in = S<T>(c, yn);
+                    a.a1 = S<T>(c, ym1);
+                    a.a2 = S<T>(c, d1);
+                    a.a3 = S<T>(c, d2);
+                    a.a4 = S<T>(c, d3);
+                    a.a5 = S<T>(c, 6);
+                    a.a6 = S<T>(c, d0);
+                } else {         // phase 2
+                    a.V = c->V_tmp;
+                    a.D = c->D_tmp;
+                    a.in = S<T>(c, d3);
+                    a.a1 = S<T>(c, ym1);
+                    a.a5 = S<T>(c, 6);
+                }
+                std::memcpy(h.data() + g.off_kp[st][ph] + i * sizeof(KPArgs<T>), &a, sizeof(a));
+                KZFastArgs<T> f;
+                std::memset(&f, 0, sizeof(f));
+                f.nxy = (long long)c->lat.nx * c->lat.ny;
+                f.ncols = c->M * c->C * f.nxy;
+                f.j0 = 0;
+                f.C = c->C;
+                const double pi = 3.14159265358979323846;
+                const double lz = c->lat.nz * c->lat.a;
+                f.cz = T(2.0 * pi * pi / (lz * lz) / c->lat.nz);
+                f.tw = reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_z;
+                f.in = a.in;
+                f.G = Gs;
+                f.ezpart = nullptr;
+                f.nu = c->C == 2 ? 1 : 2;
+                std::memcpy(h.data() + g.off_kz[st][ph] + i * sizeof(KZFastArgs<T>), &f, sizeof(f));
+            }
+}
+
+// (Re)build the groups, the z-scratch and the descriptor tables for the
+// systems' current ring states.
+int batch_build(lise_batch* b, double dt) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    b->tables = false;
+    b->groups.clear();
+    b->grouped.clear();
+    b->solo.clear();
+    const int ns = (int)b->sys.size();
+    for (int i = 0; i < ns; ++i) {
+        lise_ctx* c = b->sys[i];
+        if (!batch_groupable(c)) {
+            b->solo.push_back(i);
+            continue;
+        }
+        BatchGroup* g = nullptr;
+        for (auto& x : b->groups)
+            if (x.prec == c->prec && x.nx == c->lat.nx && x.nz == c->lat.nz) g = &x;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->prec = c->prec;
+            g->nx = c->lat.nx;
+            g->nz = c->lat.nz;
+        }
+        g->sys.push_back(i);
+        g->goff.push_back(g->gbytes);   // systems of one group may differ in C
+        g->gbytes += (size_t)c->M * c->per * c->esz;
+        g->qpwfs += c->M;
+        g->rows += (int)((c->M + c->jg - 1) / c->jg);
+        g->zblocks += (c->M * c->C * (long long)c->lat.nx * c->lat.ny * kz_lanes_of(c->lat.nz) + kThreads - 1) / kThreads;
+        b->grouped.push_back(i);
+    }
+    if (b->grouped.empty()) return LISE_OK;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return bfail(b, LISE_E_HIP, "device properties");
+    size_t gneed = 0;
+    for (auto& g : b->groups) {
+        if (g.rows > prop.maxGridSize[1])
+            return bfail(b, LISE_E_UNSUPPORTED, "group %dx%dx%d: %d workgroup rows exceed the grid limit %d", g.nx, g.nx,
+                         g.nz, g.rows, prop.maxGridSize[1]);
+        gneed = std::max(gneed, g.gbytes);
+    }
+    if (b->g_bytes < gneed) {
+        dfree(&b->G);
+        b->g_bytes = 0;
+        if (hipMalloc(&b->G, gneed) != hipSuccess) {
+            b->G = nullptr;
+            return bfail(b, LISE_E_NOMEM, "batch z-scratch of %zu bytes", gneed);
+        }
+        b->g_bytes = gneed;
+    }
+    // table layout
+    size_t off = 0;
+    for (auto& g : b->groups) {
+        const size_t n = g.sys.size();
+        const size_t kp_sz = g.prec == LISE_FP64 ? sizeof(KPArgs<double>) : sizeof(KPArgs<float>);
+        const size_t kz_sz = g.prec == LISE_FP64 ? sizeof(KZFastArgs<double>) : sizeof(KZFastArgs<float>);
+        g.off_rows = off;
+        off = align256(off + (n + 1) * sizeof(int));
+        g.off_blks = off;
+        off = align256(off + (n + 1) * sizeof(long long));
+        for (int st = 0; st < kBatchPeriod; ++st)
+            for (int ph = 0; ph < 2; ++ph) {
+                g.off_kp[st][ph] = off;
+                off = align256(off + n * kp_sz);
+                g.off_kz[st][ph] = off;
+                off = align256(off + n * kz_sz);
+            }
+    }
+    const size_t ng = b->grouped.size();
+    b->off_fblks = off;
+    off = align256(off + (ng + 1) * sizeof(long long));
+    for (int ph = 0; ph < 2; ++ph) {
+        b->off_fd[ph] = off;
+        off = align256(off + ng * sizeof(FieldsDesc));
+    }
+    b->off_tick = off;
+    off = align256(off + ng * sizeof(double*));
+    if (b->dtab_bytes < off) {
+        dfree(&b->dtab);
+        b->dtab_bytes = 0;
+        if (hipMalloc(&b->dtab, off) != hipSuccess) {
+            b->dtab = nullptr;
+            return bfail(b, LISE_E_NOMEM, "batch tables of %zu bytes", off);
+        }
+        b->dtab_bytes = off;
+    }
+    b->base_iy.assign(ns, 0);
+    b->base_dn.assign(ns, 0);
+    b->base_cfg.assign(ns, 0);
+    for (int i = 0; i < ns; ++i) {
+        b->base_iy[i] = b->sys[i]->iy;
+        b->base_dn[i] = b->sys[i]->dn;
+        b->base_cfg[i] = b->sys[i]->config_version;
+    }
+    std::vector<unsigned char> h(off, 0);
+    for (auto& g : b->groups) {
+        if (g.prec == LISE_FP64) batch_fill_group<double>(b, g, h, dt);
+        else batch_fill_group<float>(b, g, h, dt);
+    }
+    std::vector<long long> fb(ng + 1, 0);
+    std::vector<double*> tk(ng, nullptr);
+    for (size_t k = 0; k < ng; ++k) {
+        lise_ctx* c = b->sys[b->grouped[k]];
+        fb[k + 1] = fb[k] + (c->N + kFieldPts - 1) / kFieldPts;
+        tk[k] = c->dtime;
+        for (int ph = 0; ph < 2; ++ph) {
+            FieldsDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.dpart = c->dpart;
+            d.nslots = (int)((c->M + c->jg - 1) / c->jg);
+            d.N = c->N;
+            d.dens = ph == 0 ? c->dens_tmp : c->dens_cur;
+            d.V = ph == 0 ? c->V_tmp : c->V_cur;
+            d.D = ph == 0 ? c->D_tmp : c->D_cur;
+            d.fp = field_params(c);
+            d.tdev = c->dtime;
+            d.bad = c->bad;
+            std::memcpy(h.data() + b->off_fd[ph] + k * sizeof(FieldsDesc), &d, sizeof(d));
+        }
+    }
+    b->fblocks = fb[ng];
+    std::memcpy(h.data() + b->off_fblks, fb.data(), fb.size() * sizeof(long long));
+    std::memcpy(h.data() + b->off_tick, tk.data(), tk.size() * sizeof(double*));
+    // the batch stream may still run earlier steps that read the old tables
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipMemcpy(b->dtab, h.data(), off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "batch tables: %s", hipGetErrorString(e));
+    b->tables = true;
+    b->tab_dt = dt;
+    b->tphase = 0;
+    return LISE_OK;
+}
+
+// Whether the tables still describe every grouped system: same tuning, dt,
+// and each ring advanced by exactly tphase steps from the base.
+bool batch_tables_valid(const lise_batch* b, double dt) {
+    if (!b->tables || b->tab_dt != dt) return false;
+    for (int i : b->grouped) {
+        const lise_ctx* c = b->sys[i];
+        int iy, dn;
+        batch_ring(b, i, b->tphase, &iy, &dn);
+        if (c->config_version != b->base_cfg[i] || c->iy != iy || c->dn != dn || !batch_groupable(c)) return false;
+    }
+    for (int i : b->solo)
+        if (batch_groupable(b->sys[i])) return false;
+    return true;
+}
+
+template <typename T, int MODE, int NS>
+void launch_kp_batch_n(lise_batch* b, const BatchGroup& g, int st, const cpx<T>* twN, hipStream_t s) {
+    constexpr int block = plane_block<T, NS>();
+    const size_t lds = std::max(kp_fast_lds<T, NS>(), (size_t)block * sizeof(double));
+    const char* base = static_cast<const char*>(b->dtab);
+    const auto* tab = reinterpret_cast<const KPArgs<T>*>(base + g.off_kp[st][MODE == KP_ABM1 ? 0 : 1]);
+    const auto* rows = reinterpret_cast<const int*>(base + g.off_rows);
+    hipLaunchKernelGGL((kp_fast_batch<T, NS, MODE>), dim3((unsigned)g.nz, (unsigned)g.rows), dim3(block), lds, s, tab,
+                       rows, (int)g.sys.size(), twN);
+}
+
+template <typename T, int MODE>
+int launch_kp_batch(lise_batch* b, const BatchGroup& g, int st, hipStream_t s) {
+    const lise_ctx* c0 = b->sys[g.sys[0]];
+    const cpx<T>* twN = reinterpret_cast<const cpx<T>*>(c0->tw) + c0->tw_full_xy;
+    hipEvent_t ev;
+    bprof_begin(b, &ev, s);
+    switch (g.nx) {
+        case 8: launch_kp_batch_n<T, MODE, 8>(b, g, st, twN, s); break;
+        case 16: launch_kp_batch_n<T, MODE, 16>(b, g, st, twN, s); break;
+        case 20: launch_kp_batch_n<T, MODE, 20>(b, g, st, twN, s); break;
+        case 24: launch_kp_batch_n<T, MODE, 24>(b, g, st, twN, s); break;
+        case 32: launch_kp_batch_n<T, MODE, 32>(b, g, st, twN, s); break;
+        case 48: launch_kp_batch_n<T, MODE, 48>(b, g, st, twN, s); break;
+        default: launch_kp_batch_n<T, MODE, 64>(b, g, st, twN, s); break;
+    }
+    bprof_end(b, MODE == KP_ABM1 ? 0 : 3, ev, s);
+    return bcheck_launch(b, "kp_fast_batch");
+}
+
+template <typename T, int NZ>
+void launch_kz_batch_n(lise_batch* b, const BatchGroup& g, int st, int ph, bool nt, hipStream_t s) {
+    constexpr int L = kz_lanes<NZ>();
+    const char* base = static_cast<const char*>(b->dtab);
+    const auto* tab = reinterpret_cast<const KZFastArgs<T>*>(base + g.off_kz[st][ph]);
+    const auto* blks = reinterpret_cast<const long long*>(base + g.off_blks);
+    const dim3 grid((unsigned)g.zblocks);
+    if (nt)
+        hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, true>), grid, dim3(kThreads), 0, s, tab, blks, (int)g.sys.size());
+    else
+        hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, false>), grid, dim3(kThreads), 0, s, tab, blks, (int)g.sys.size());
+}
+
+template <typename T>
+int launch_kz_batch(lise_batch* b, const BatchGroup& g, int st, int ph, hipStream_t s) {
+    const bool nt = b->sys[g.sys[0]]->stream_hint;
+    hipEvent_t ev;
+    bprof_begin(b, &ev, s);
+    switch (g.nz) {
+        case 8: launch_kz_batch_n<T, 8>(b, g, st, ph, nt, s); break;
+        case 16: launch_kz_batch_n<T, 16>(b, g, st, ph, nt, s); break;
+        case 20: launch_kz_batch_n<T, 20>(b, g, st, ph, nt, s); break;
+        case 24: launch_kz_batch_n<T, 24>(b, g, st, ph, nt, s); break;
+        case 32: launch_kz_batch_n<T, 32>(b, g, st, ph, nt, s); break;
+        case 48: launch_kz_batch_n<T, 48>(b, g, st, ph, nt, s); break;
+        default: launch_kz_batch_n<T, 64>(b, g, st, ph, nt, s); break;
+    }
+    bprof_end(b, 1, ev, s);
+    return bcheck_launch(b, "kz_fast_batch");
+}
+
+template <typename T>
+int batch_phase_group(lise_batch* b, const BatchGroup& g, int st, int ph, hipStream_t s) {
+    BCHK(launch_kz_batch<T>(b, g, st, ph, s));
+    return ph == 0 ? launch_kp_batch<T, KP_ABM1>(b, g, st, s) : launch_kp_batch<T, KP_ABM2>(b, g, st, s);
+}
+
+// One ABM step of every grouped system (the enqueue only): per phase, the
+// z-axis and plane launches of each group, then one density + fields launch
+// for all systems; last, every system's time advances by dt.  `st` is the
+// step's place in the ring period relative to the tables' base state.
+int batch_step_grouped(lise_batch* b, int st, hipStream_t s) {
+    const char* base = static_cast<const char*>(b->dtab);
+    for (int ph = 0; ph < 2; ++ph) {
+        for (const auto& g : b->groups) {
+            if (g.prec == LISE_FP64) BCHK(batch_phase_group<double>(b, g, st, ph, s));
+            else BCHK(batch_phase_group<float>(b, g, st, ph, s));
+        }
+        hipEvent_t ev;
+        bprof_begin(b, &ev, s);
+        hipLaunchKernelGGL(fields_batch_kernel, dim3((unsigned)b->fblocks), dim3(kFieldPts * kFieldGroups), 0, s,
+                           reinterpret_cast<const FieldsDesc*>(base + b->off_fd[ph]),
+                           reinterpret_cast<const long long*>(base + b->off_fblks), (int)b->grouped.size(), b->tab_dt);
+        bprof_end(b, 2, ev, s);
+        BCHK(bcheck_launch(b, "fields_batch_kernel"));
+    }
+    const int n = (int)b->grouped.size();
+    hipLaunchKernelGGL(tick_batch_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s,
+                       reinterpret_cast<double* const*>(base + b->off_tick), n, b->tab_dt);
+    return bcheck_launch(b, "tick_batch_kernel");
+}
+
+void batch_advance_host(lise_batch* b) {
+    for (int i : b->grouped) advance_host(b->sys[i], b->tab_dt);
+    b->tphase = (b->tphase + 1) % kBatchPeriod;
+}
+
+// Capture one ring period of grouped steps (starting at tphase 0) on the
+// internal stream: kernel nodes only, no events or forks inside the capture.
+int batch_capture(lise_batch* b) {
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    hipError_t e = hipEventRecord(b->ev_cap, b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->ev_cap, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "begin capture: %s", hipGetErrorString(e));
+    const bool prof = b->prof.on;
+    b->prof.on = false;
+    int rc = LISE_OK;
+    for (int st = 0; st < kBatchPeriod && rc == LISE_OK; ++st) rc = batch_step_grouped(b, st, b->cap);
+    b->prof.on = prof;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap, &g);
+    if (rc != LISE_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != LISE_OK) return rc;
+        return bfail(b, LISE_E_HIP, "end capture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, LISE_E_HIP, "graph instantiation: %s", hipGetErrorString(e));
+    }
+    return LISE_OK;
 }
 
 // ---- checkpoint files ----------------------------------------------------------------
@@ -1723,7 +2157,7 @@ int lise_profile(lise_ctx* c, int32_t enable) {
 }
 
 int lise_profile_read(lise_ctx* c, int32_t which, int64_t* launches, double* total_ms) {
-    if (!c || which < 0 || which > 3) return LISE_E_ARG;
+    if (!c || which < 0 || which > 4) return LISE_E_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (auto& r : c->prof.recs) {
         float ms = 0.0f;
@@ -1874,13 +2308,8 @@ int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, voi
             }
         b->sys.push_back(ctxs[i]);
     }
-    b->fork.assign(nsys, nullptr);
-    b->ev_join.assign(nsys, nullptr);
-    hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-    for (int i = 0; i < nsys && e == hipSuccess; ++i) {
-        e = hipStreamCreateWithFlags(&b->fork[i], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming);
-    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_cap, hipEventDisableTiming);
     if (e != hipSuccess) {
         lise_batch_free(b);
         return LISE_E_HIP;
@@ -1894,43 +2323,103 @@ int lise_batch_create(lise_batch** out, int32_t nsys, lise_ctx* const* ctxs, voi
     return LISE_OK;
 }
 
+int lise_batch_set_graph(lise_batch* b, int32_t enable) {
+    if (!b || (enable != 0 && enable != 1)) return LISE_E_ARG;
+    b->use_graph = enable;
+    return LISE_OK;
+}
+
 int lise_batch_step(lise_batch* b, double dt, int64_t nsteps) {
     if (!b) return LISE_E_ARG;
     if (!std::isfinite(dt) || dt == 0.0 || nsteps < 0) return bfail(b, LISE_E_ARG, "bad dt or nsteps");
-    for (size_t i = 0; i < b->sys.size(); ++i)
-        if (b->sys[i]->n_set < b->sys[i]->M) return bfail(b, LISE_E_STATE, "system %zu: qpwfs not fully set", i);
-    // fork: every system stream starts after the caller's earlier work
-    hipError_t ef = hipEventRecord(b->ev_fork, b->stream);
-    if (ef != hipSuccess) return bfail(b, LISE_E_HIP, "fork: %s", hipGetErrorString(ef));
-    int rc = LISE_OK;
-    size_t i = 0;
-    for (; i < b->sys.size(); ++i) {
+    for (size_t i = 0; i < b->sys.size(); ++i) {
         lise_ctx* c = b->sys[i];
-        hipError_t e = hipStreamWaitEvent(b->fork[i], b->ev_fork, 0);
-        if (e != hipSuccess) {
-            rc = bfail(b, LISE_E_HIP, "fork of system %zu: %s", i, hipGetErrorString(e));
-            break;
-        }
-        c->stream = b->fork[i];
-        rc = advance_any(c, dt, nsteps);
-        if (rc != LISE_OK) {
-            bfail(b, rc, "system %zu: %s", i, c->err);
-            ++i;
-            break;
-        }
-    }
-    // join every forked stream back into the caller's stream, also on failure
-    for (size_t k = 0; k < i; ++k) {
-        lise_ctx* c = b->sys[k];
-        hipError_t e = hipEventRecord(b->ev_join[k], b->fork[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_join[k], 0);
         c->stream = b->stream;
-        if (e != hipSuccess && rc == LISE_OK) rc = bfail(b, LISE_E_HIP, "join of system %zu: %s", k, hipGetErrorString(e));
+        if (c->n_set < c->M) return bfail(b, LISE_E_STATE, "system %zu: qpwfs not fully set", i);
     }
-    if (rc != LISE_OK) return rc;
+    // start-up where a system has no history for this dt (one system at a time)
+    for (size_t i = 0; i < b->sys.size(); ++i) {
+        lise_ctx* c = b->sys[i];
+        if (c->hist && c->dt_hist == dt) continue;
+        int rc = c->prec == LISE_FP64 ? startup_t<double>(c, dt) : startup_t<float>(c, dt);
+        if (rc != LISE_OK) return bfail(b, rc, "system %zu start-up: %s", i, c->err);
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+    }
+    if (!batch_tables_valid(b, dt)) BCHK(batch_build(b, dt));
+    if (!b->grouped.empty()) {
+        long long left = nsteps;
+        // eager steps up to the start of a ring period, then graph replays
+        while (left > 0 && (b->tphase != 0 || !b->use_graph || b->prof.on || left < kBatchPeriod)) {
+            BCHK(batch_step_grouped(b, b->tphase, b->stream));
+            batch_advance_host(b);
+            --left;
+        }
+        if (left >= kBatchPeriod) {
+            if (!b->gexec) BCHK(batch_capture(b));
+            for (; left >= kBatchPeriod; left -= kBatchPeriod) {
+                hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+                if (e != hipSuccess) return bfail(b, LISE_E_HIP, "graph launch: %s", hipGetErrorString(e));
+                for (int k = 0; k < kBatchPeriod; ++k) batch_advance_host(b);
+            }
+        }
+        for (; left > 0; --left) {
+            BCHK(batch_step_grouped(b, b->tphase, b->stream));
+            batch_advance_host(b);
+        }
+    }
+    for (int i : b->solo) {
+        lise_ctx* c = b->sys[i];
+        int rc = advance_any(c, dt, nsteps);
+        if (rc != LISE_OK) return bfail(b, rc, "system %d: %s", i, c->err);
+    }
     for (size_t k = 0; k < b->sys.size(); ++k) {
-        rc = check_bad(b->sys[k]);
+        int rc = check_bad(b->sys[k]);
         if (rc != LISE_OK) return bfail(b, rc, "system %zu: %s", k, b->sys[k]->err);
+    }
+    return LISE_OK;
+}
+
+int lise_batch_info(const lise_batch* b, int32_t* ngroups, int32_t* nsolo) {
+    if (!b) return LISE_E_ARG;
+    if (ngroups) *ngroups = (int32_t)b->groups.size();
+    if (nsolo) *nsolo = (int32_t)b->solo.size();
+    return LISE_OK;
+}
+
+int lise_batch_profile(lise_batch* b, int32_t enable) {
+    if (!b) return LISE_E_ARG;
+    if (enable && b->prof.pool.empty()) {
+        b->prof.pool.resize(1 << 14);
+        for (auto& ev : b->prof.pool)
+            if (hipEventCreate(&ev) != hipSuccess) return bfail(b, LISE_E_HIP, "event pool");
+    }
+    b->prof.on = enable != 0;
+    return LISE_OK;
+}
+
+int lise_batch_profile_read(lise_batch* b, int32_t which, int64_t* launches, double* total_ms) {
+    if (!b || which < 0 || which > 3) return LISE_E_ARG;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LISE_E_HIP, "%s", hipGetErrorString(e));
+    for (auto& r : b->prof.recs) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return bfail(b, LISE_E_HIP, "%s", hipGetErrorString(e));
+        b->prof.total_ms[r.cls] += ms;
+        b->prof.count[r.cls] += 1;
+    }
+    b->prof.recs.clear();
+    b->prof.used = 0;
+    if (launches) *launches = b->prof.count[which];
+    if (total_ms) *total_ms = b->prof.total_ms[which];
+    b->prof.total_ms[which] = 0.0;
+    b->prof.count[which] = 0;
+    if (b->prof.overflow) {
+        b->prof.overflow = false;
+        return bfail(b, LISE_E_STATE, "profiling event pool exhausted: read the counters more often");
     }
     return LISE_OK;
 }
@@ -1941,13 +2430,13 @@ void lise_batch_free(lise_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     else (void)hipDeviceSynchronize();
-    for (hipStream_t s : b->fork)
-        if (s) (void)hipStreamSynchronize(s);
-    for (hipStream_t s : b->fork)
-        if (s) (void)hipStreamDestroy(s);
-    for (hipEvent_t e : b->ev_join)
-        if (e) (void)hipEventDestroy(e);
-    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->ev_cap) (void)hipEventDestroy(b->ev_cap);
+    for (auto& ev : b->prof.pool) (void)hipEventDestroy(ev);
+    dfree(&b->G);
+    dfree(&b->dtab);
     delete b;
 }
 

@@ -926,13 +926,14 @@ __device__ __forceinline__ double ext_potential(const FieldParams& f, long long 
 // (a fixed order: bitwise reproducible), then forms the fields.
 constexpr int kFieldPts = 64;
 constexpr int kFieldGroups = 16;
-__global__ void __launch_bounds__(kFieldPts * kFieldGroups) fields_kernel(
+// blk: the workgroup's block of kFieldPts points within the system
+__device__ __forceinline__ void fields_body(
     const double* __restrict__ dpart, int nslots, long long N, const double* __restrict__ avg_with,
-    double* __restrict__ dens_out, double* __restrict__ V, double* __restrict__ D, FieldParams fp,
-    const double* __restrict__ tdev, double toff, int* __restrict__ bad) {
+    double* __restrict__ dens_out, double* __restrict__ V, double* __restrict__ D, const FieldParams& fp,
+    const double* __restrict__ tdev, double toff, int* __restrict__ bad, long long blk) {
     __shared__ double part[3][kFieldGroups][kFieldPts];
     const int pt = threadIdx.x % kFieldPts, g = threadIdx.x / kFieldPts;
-    const long long r = (long long)blockIdx.x * kFieldPts + pt;
+    const long long r = blk * kFieldPts + pt;
     if (nslots > 0) {
         double n = 0.0, kr = 0.0, ki = 0.0;
         if (r < N) {
@@ -987,6 +988,41 @@ __global__ void __launch_bounds__(kFieldPts * kFieldGroups) fields_kernel(
     V[r] = U + ext_potential(fp, r, ext_ramp(fp, t));
     D[2 * r] = dre;
     D[2 * r + 1] = dim;
+}
+
+__global__ void __launch_bounds__(kFieldPts * kFieldGroups) fields_kernel(
+    const double* __restrict__ dpart, int nslots, long long N, const double* __restrict__ avg_with,
+    double* __restrict__ dens_out, double* __restrict__ V, double* __restrict__ D, FieldParams fp,
+    const double* __restrict__ tdev, double toff, int* __restrict__ bad) {
+    fields_body(dpart, nslots, N, avg_with, dens_out, V, D, fp, tdev, toff, bad, (long long)blockIdx.x);
+}
+
+// One system's part of a batched density reduction + fields launch.
+struct FieldsDesc {
+    const double* dpart;
+    int nslots;
+    long long N;
+    double* dens;
+    double* V;
+    double* D;
+    FieldParams fp;
+    const double* tdev;
+    int* bad;
+};
+
+// Every system of a batch in one launch: blks[s] is the first workgroup of
+// system s (blks[nsys] = gridDim.x).  No averaging (ABM phases only).
+__global__ void __launch_bounds__(kFieldPts * kFieldGroups) fields_batch_kernel(
+    const FieldsDesc* __restrict__ tab, const long long* __restrict__ blks, int nsys, double toff) {
+    int lo = 0, hi = nsys;
+    const long long b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blks[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const FieldsDesc& d = tab[lo];
+    fields_body(d.dpart, d.nslots, d.N, nullptr, d.dens, d.V, d.D, d.fp, d.tdev, toff, d.bad, b - blks[lo]);
 }
 
 // Observables of the fields: per-block partial sums of
@@ -1086,6 +1122,12 @@ __global__ void __launch_bounds__(256) convert_kernel(const cpx<TI>* __restrict_
 // Advance the device-side time of a system by dt (one thread).
 __global__ void tick_kernel(double* __restrict__ t, double dt) {
     if (blockIdx.x == 0 && threadIdx.x == 0) t[0] = t[0] + dt;
+}
+
+// t_n -> t_n + dt for the device-side times of n systems
+__global__ void tick_batch_kernel(double* const* __restrict__ t, int n, double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) t[i][0] = t[i][0] + dt;
 }
 
 __global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ p, long long n) {

@@ -269,12 +269,12 @@ struct KZFastArgs {
     int nu;
 };
 
+// col: the column of this thread within the launch's K * C * nx * ny columns
 template <typename T, int NZ, bool NT>
-__global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
+__device__ __forceinline__ void kz_fast_body(const KZFastArgs<T>& a, const long long col) {
     __shared__ cpx<T> tab[NZ];
     for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
     __syncthreads();
-    const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= a.ncols) return;
     const long long jc = col / a.nxy, r = col - jc * a.nxy;
     const cpx<T>* src = a.in + (a.j0 * a.C + jc) * NZ * a.nxy + r;
@@ -297,6 +297,11 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
     for (int z = 0; z < NZ; ++z) st_hint<T, NT>(dst + z * a.nxy, x[z]);
 }
 
+template <typename T, int NZ, bool NT>
+__global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
+    kz_fast_body<T, NZ, NT>(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // z axis with a column split over L adjacent lanes (lane s holds z = s + L q,
 // q < NZ / L): the line transform of the plane kernel (lane_fwd / lane_inv)
 // along z.  A wave reads L contiguous runs of 64 / L columns per load; the
@@ -314,13 +319,13 @@ constexpr int kz_lanes() {
     return kz_lanes_of(NZ);
 }
 
+// t: the thread index within the launch (L threads per column)
 template <typename T, int NZ, int L, bool NT>
-__global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
+__device__ __forceinline__ void kz_lanes_body(const KZFastArgs<T>& a, const long long t) {
     constexpr int P = NZ / L;
     __shared__ cpx<T> tab[NZ];
     for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
     __syncthreads();
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long col = t / L;
     const int s = (int)(t % L);
     // the L lanes of a column are adjacent and L divides 64: a column is
@@ -347,6 +352,35 @@ __global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
     lane_inv<T, P, L>(x, tab, s);
 #pragma unroll
     for (int q = 0; q < P; ++q) st_hint<T, NT>(dst + (s + L * q) * a.nxy, x[q]);
+}
+
+template <typename T, int NZ, int L, bool NT>
+__global__ void __launch_bounds__(256) kz_lanes_kernel(const KZFastArgs<T> a) {
+    kz_lanes_body<T, NZ, L, NT>(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Systems of one z side advanced by one launch: tab[s] describes system s,
+// blks[s] is its first workgroup (blks[nsys] = gridDim.x); a system's threads
+// start at a workgroup boundary, so every workgroup belongs to one system.
+__device__ __forceinline__ int batch_find_ll(const long long* __restrict__ blks, int nsys, long long b) {
+    int lo = 0, hi = nsys;   // blks[lo] <= b < blks[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blks[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int NZ, int L, bool NT>
+__global__ void __launch_bounds__(256) kz_fast_batch(const KZFastArgs<T>* __restrict__ tab,
+                                                     const long long* __restrict__ blks, int nsys) {
+    const int s = batch_find_ll(blks, nsys, (long long)blockIdx.x);
+    const long long t = ((long long)blockIdx.x - blks[s]) * blockDim.x + threadIdx.x;
+    if constexpr (L > 1)
+        kz_lanes_body<T, NZ, L, NT>(tab[s], t);
+    else
+        kz_fast_body<T, NZ, NT>(tab[s], t);
 }
 
 // Total current along z by Parseval (Eq. j summed over the lattice): per
@@ -541,8 +575,10 @@ __device__ __forceinline__ double eta_local(const KPArgs<T>& a, int pr, double s
            2.0 * (Dr * (ur * vr + ui * vi) - Di * (ur * vi - ui * vr));
 }
 
+// The body of the plane kernel: `a` describes one system, `by` is the
+// workgroup row (group of jg qpwfs) within that system's launch.
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
+__device__ __forceinline__ void kp_fast_body(const KPArgs<T>& a, const cpx<T>* __restrict__ twN, const int by) {
     constexpr int L = plane_lanes<T, N>();
     constexpr int P = N / L;
     constexpr bool NT = plane_stream_hint<T, N>();
@@ -567,7 +603,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     const int brs = bitrev(s, L);
     constexpr long long nxy = (long long)N * N;
     const long long N3 = nxy * a.nz;
-    const int jbeg = blockIdx.y * a.jg;
+    const int jbeg = by * a.jg;
     const int jend = min(a.kcount, jbeg + a.jg);
     const T cdt = T(a.dt / 48.0);
     const cpx<T> coef = mk(T(a.coef_re), T(a.coef_im));
@@ -740,7 +776,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     if constexpr (MODE == KP_ETAXY) return;
     if (MODE == KP_KINETIC || MODE == KP_ETA) {
         double* red = reinterpret_cast<double*>(smem_raw);
-        const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const long long wg = (long long)by * gridDim.x + blockIdx.x;
         const int nsum = (MODE == KP_KINETIC && a.ppart) ? 3 : 1;
         for (int v = 0; v < nsum; ++v) {
             red[tid] = v == 0 ? ekin : (v == 1 ? pxs : pys);
@@ -761,7 +797,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     }
     if constexpr (NAT) {
         if (a.dens_src) {
-            double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
+            double* base = a.dpart + (long long)by * 3 * N3 + (long long)z * nxy;
 #pragma unroll
             for (int i = 0; i < PN; ++i) {
                 const int p = tid + i * NTH;
@@ -778,7 +814,7 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             }
         }
     } else if (a.dens_src && act) {
-        double* base = a.dpart + (long long)blockIdx.y * 3 * N3 + (long long)z * nxy;
+        double* base = a.dpart + (long long)by * 3 * N3 + (long long)z * nxy;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int pt = row * N + s + L * q;
@@ -793,6 +829,33 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
             }
         }
     }
+}
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_fast(const KPArgs<T> a, const cpx<T>* __restrict__ twN) {
+    kp_fast_body<T, N, MODE>(a, twN, (int)blockIdx.y);
+}
+
+// Systems of one lattice side advanced by one launch: tab[s] describes system
+// s (its buffers, fields, functional and qpwf count), rows[s] is the first
+// workgroup row of system s (rows[nsys] = gridDim.y).  Each workgroup finds
+// its system by bisection over rows; all its threads take the same branch.
+__device__ __forceinline__ int batch_find(const int* __restrict__ rows, int nsys, int y) {
+    int lo = 0, hi = nsys;   // rows[lo] <= y < rows[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rows[mid] <= y) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES)
+    kp_fast_batch(const KPArgs<T>* __restrict__ tab, const int* __restrict__ rows, int nsys,
+                  const cpx<T>* __restrict__ twN) {
+    const int s = batch_find(rows, nsys, (int)blockIdx.y);
+    kp_fast_body<T, N, MODE>(tab[s], twN, (int)blockIdx.y - rows[s]);
 }
 
 }  // namespace lise

@@ -23,7 +23,8 @@ SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
            "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune", "lise_coupling",
            "lise_save", "lise_load", "lise_kick", "lise_current",
-           "lise_batch_create", "lise_batch_step", "lise_batch_last_error", "lise_batch_free"]
+           "lise_batch_create", "lise_batch_step", "lise_batch_set_graph", "lise_batch_info",
+           "lise_batch_profile", "lise_batch_profile_read", "lise_batch_last_error", "lise_batch_free"]
 
 
 class Lattice(ct.Structure):
@@ -104,6 +105,10 @@ def load_library(path=LIB_PATH):
         "lise_coupling": ([ct.POINTER(Lattice), ct.POINTER(Functional), ct.POINTER(ct.c_double)], ct.c_int),
         "lise_batch_create": ([ct.POINTER(P), ct.c_int32, ct.POINTER(P), P], ct.c_int),
         "lise_batch_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
+        "lise_batch_set_graph": ([P, ct.c_int32], ct.c_int),
+        "lise_batch_info": ([P, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)], ct.c_int),
+        "lise_batch_profile": ([P, ct.c_int32], ct.c_int),
+        "lise_batch_profile_read": ([P, ct.c_int32, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)], ct.c_int),
         "lise_batch_last_error": ([P], ct.c_char_p),
         "lise_batch_free": ([P], None),
     }
@@ -281,7 +286,9 @@ class Context:
 
 
 class Batch:
-    """Independent systems advanced together by one graph per four ABM steps."""
+    """Independent systems advanced together: systems of one lattice side and
+    precision share one z-axis and one plane-kernel launch per ABM phase, and
+    four steps replay as one captured graph."""
 
     def __init__(self, contexts, stream=None):
         self.lib = load_library()
@@ -292,11 +299,33 @@ class Batch:
         if rc != 0:
             raise LiseError(f"lise_batch_create failed: {ERRORS.get(rc, rc)}")
 
-    def step(self, dt, nsteps):
-        rc = self.lib.lise_batch_step(self._h, dt, nsteps)
+    def _check(self, rc, what):
         if rc != 0:
             msg = self.lib.lise_batch_last_error(self._h).decode()
-            raise LiseError(f"lise_batch_step: {ERRORS.get(rc, rc)}: {msg}")
+            raise LiseError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+    def step(self, dt, nsteps):
+        self._check(self.lib.lise_batch_step(self._h, dt, nsteps), "lise_batch_step")
+
+    def set_graph(self, enable):
+        self._check(self.lib.lise_batch_set_graph(self._h, int(bool(enable))), "lise_batch_set_graph")
+
+    def info(self):
+        """(number of groups, number of systems stepped one by one) of the last step."""
+        g, s = ct.c_int32(), ct.c_int32()
+        self._check(self.lib.lise_batch_info(self._h, ct.byref(g), ct.byref(s)), "lise_batch_info")
+        return g.value, s.value
+
+    def profile(self, enable):
+        self._check(self.lib.lise_batch_profile(self._h, int(bool(enable))), "lise_batch_profile")
+
+    def profile_read(self, which):
+        """(launches, total ms) of kernel class which: 0 plane kernel of ABM phase 1,
+        1 z axis, 2 fields, 3 plane kernel of ABM phase 2."""
+        n, ms = ct.c_int64(), ct.c_double()
+        self._check(self.lib.lise_batch_profile_read(self._h, which, ct.byref(n), ct.byref(ms)),
+                    "lise_batch_profile_read")
+        return n.value, ms.value
 
     def close(self):
         if self._h:

@@ -725,35 +725,6 @@ def test_kick_and_current_fp32_four_components(lise):
     assert np.allclose(obs["v_cm"], o["v_cm"], rtol=1e-5, atol=1e-9)
 
 
-def test_batch_with_options_matches_individual(lise):
-    """A batch mixing phase removal, the regularised coupling and plain systems equals
-    stepping each alone (per-system graphs on), bit for bit."""
-    ws = [wl.config2(M=16, n=16), wl.config3(M=12, n=20, precision=wl.FP32), wl.config1(M=32)]
-    ws[0].functional.remove_phase = 1
-    ws[1].functional.regularize = 1
-    dt = 0.002
-    say("batch with options: 3 systems, 9 steps")
-    ctxs = []
-    for w in ws:
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_tuning(graph=1)
-        c.set_qpwf(0, w.qpwfs())
-        ctxs.append(c)
-    b = lise.Batch(ctxs)
-    b.step(dt, 9)
-    got = [c.get_qpwf(0, w.M) for c, w in zip(ctxs, ws)]
-    b.close()
-    for c in ctxs:
-        c.close()
-    for w, g in zip(ws, got):
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_qpwf(0, w.qpwfs())
-        c.step(dt, 9)
-        ref = c.get_qpwf(0, w.M)
-        c.close()
-        assert np.array_equal(g, ref), w.name
-
-
 def test_checkpoint_errors(lise, tmp_path):
     w = wl.config1(M=16)
     path = str(tmp_path / "e.ckpt")
@@ -769,87 +740,6 @@ def test_checkpoint_errors(lise, tmp_path):
     with pytest.raises(lise.LiseError, match="ARG"):
         other.load(str(tmp_path / "missing.ckpt"))
     other.close()
-
-
-def batch_systems():
-    specs = [(wl.config1(M=64), wl.FP64), (wl.config2(M=24, n=16), wl.FP64),
-             (wl.config3(M=16, n=20, precision=wl.FP32), wl.FP32), (wl.config4(M=12, n=8, precision=wl.FP64), wl.FP64)]
-    out = []
-    for w, prec in specs:
-        w.functional.precision = prec
-        out.append(w)
-    return out
-
-
-@pytest.mark.skip(reason="capturing all systems of a batch into one graph crashed the host process "
-                         "(SIGSEGV inside lise_batch_step); that capture is removed and its cause was not shown. "
-                         "test_batch_per_system_streams_bitwise covers the batch path that replaced it")
-def test_batch_matches_individual_systems_bitwise(lise):
-    """A batch of uneven systems (lattices 8^3..20^3, C = 2 and 4, FP64 and FP32) stepped
-    through one graph equals each system stepped alone."""
-    systems = batch_systems()
-    dt = 0.002
-    say("batch of 4 systems, 10 steps")
-    ctxs = []
-    for w in systems:
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_qpwf(0, w.qpwfs())
-        ctxs.append(c)
-    b = lise.Batch(ctxs)
-    b.step(dt, 10)
-    got = [c.get_qpwf(0, w.M) for c, w in zip(ctxs, systems)]
-    b.close()
-    for c in ctxs:
-        c.close()
-    for w, g in zip(systems, got):
-        say(f"  alone: {w.name}")
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_qpwf(0, w.qpwfs())
-        c.step(dt, 10)
-        ref = c.get_qpwf(0, w.M)
-        c.close()
-        assert np.array_equal(g, ref), w.name
-    # and one of them against the oracle
-    w = systems[1]
-    ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
-    ev.step(dt, 10)
-    assert rel_l2(got[1], ev.y) < 1e-11
-
-
-def test_batch_per_system_streams_bitwise(lise):
-    """A batch of uneven systems (lattices 8^3..20^3, C = 2 and 4, FP64 and FP32), each on
-    its own forked stream with its own four-step graph replays, equals each system stepped
-    alone; a second call continues from the first."""
-    systems = batch_systems()
-    dt = 0.002
-    say("batch of 4 systems on forked streams, 10 + 5 steps")
-    ctxs = []
-    for w in systems:
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_qpwf(0, w.qpwfs())
-        ctxs.append(c)
-    b = lise.Batch(ctxs)
-    b.step(dt, 10)
-    b.step(dt, 5)
-    got = [(c.get_qpwf(0, w.M), c.time()) for c, w in zip(ctxs, systems)]
-    b.close()
-    for c in ctxs:
-        c.close()
-    for w, (g, t) in zip(systems, got):
-        say(f"  alone: {w.name}")
-        c = lise.Context(w.lattice, w.M, w.functional)
-        c.set_qpwf(0, w.qpwfs())
-        c.step(dt, 10)
-        c.step(dt, 5)
-        ref = c.get_qpwf(0, w.M)
-        tref = c.time()
-        c.close()
-        assert t == tref, w.name
-        assert np.array_equal(g, ref), w.name
-    w = systems[1]
-    ev = oracle.Evolver(w.lattice, w.functional, w.qpwfs())
-    ev.step(dt, 15)
-    assert rel_l2(got[1][0], ev.y) < 1e-11
 
 
 def test_autotune_runs_and_keeps_invariants(lise):
