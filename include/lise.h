@@ -208,6 +208,22 @@ int lise_get_qpwf(lise_ctx *c, int64_t first, int64_t count, void *dst, int32_t 
  * host).  Errors: ARG, STATE, HIP. */
 int lise_apply_h(lise_ctx *c, int64_t first, int64_t count, void *out, int32_t out_is_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): lise_apply_h with
+ * a device output that calls no hipMalloc, hipFree or allocating routine.
+ * `out_device` receives count*C*N complex128 values (caller-owned device
+ * memory).  H psi is staged, in pieces, through one fixed device array of
+ * LISE_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the
+ * process ends (lise_apply_h instead allocates a staging buffer of its own at
+ * its first call); results equal lise_apply_h bit for bit.  The array is
+ * shared by every context and call on that GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (different streams or host
+ * threads) race.  The context, its fields and z-term scratch are allocated
+ * by lise_init, before.  Errors: ARG, STATE, UNSUPPORTED (one qpwf, C*N
+ * elements of the state's precision, larger than the array), HIP. */
+#define LISE_NOALLOC_SCRATCH_BYTES (64 << 20)
+int lise_apply_h_noalloc(lise_ctx *c, int64_t first, int64_t count, void *out_device);
+
 /* Series-expansion start-up (Sec. "Time evolution"): three predictor-
  * corrector steps of order 4 with corrector densities (n_pre + n)/2 taken at
  * t + dt/2; stores y'_0, y'_1, y'_2 = -i H y_s, y_2, y_3 and p_3 - c_3 = 0.

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -31,6 +32,16 @@ constexpr int kThreads = 256;
 const char* kVersion = "lise-mi355x 0.1 (gfx950)";
 constexpr int kBatchPeriod = 4;   // ABM steps after which the buffer ring repeats
 
+// Staging memory of lise_apply_h_noalloc: one fixed array per GPU, held until
+// the process ends, shared by every context on that GPU.  Host code never
+// uses the name `scratch` as an address (in host code it is a stand-in, not
+// device memory); it uses the address hipGetSymbolAddress returned for the
+// device, recorded once per device by lise_init.
+constexpr size_t kScratchBytes = (size_t)LISE_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+void* g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
 struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
@@ -43,6 +54,8 @@ struct Prof {
 };
 
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct lise_ctx {
     lise_lattice lat;
@@ -77,6 +90,7 @@ struct lise_ctx {
     void* tw = nullptr;
     void* ah_buf = nullptr;    // staging of lise_apply_h (one piece, kept)
     size_t ah_cap = 0;
+    void* scratch_dev = nullptr;  // this device's address of `scratch` (lise_apply_h_noalloc)
     double* red = nullptr;     // reduction partials (observables)
     long long red_cap = 0;
     double* pz_part = nullptr;  // per-workgroup z-momentum sums (observables)
@@ -984,6 +998,20 @@ int apply_h_t(lise_ctx* c, long long first, long long count, void* out, int out_
     void* stage = c->ah_buf;
     void* stage64 = sizeof(T) == 8 ? stage : static_cast<char*>(c->ah_buf) + st_bytes;
     return apply_pieces_t<T>(c, first, count, piece, stage, stage64, out, out_is_device);
+}
+
+// lise_apply_h_noalloc: the same pieces, staged through this device's fixed
+// array (kScratchBytes) instead of the context's buffer; the output is device
+// memory, so the piece is widened straight into it.  Allocates nothing.
+template <typename T>
+int apply_h_noalloc_t(lise_ctx* c, long long first, long long count, void* out) {
+    const size_t per_bytes = (size_t)c->per * c->esz;
+    if (per_bytes > kScratchBytes)
+        return fail(c, LISE_E_UNSUPPORTED, "one qpwf of H psi (%zu bytes) exceeds the %zu-byte fixed staging array",
+                    per_bytes, kScratchBytes);
+    if (!c->scratch_dev) return fail(c, LISE_E_STATE, "fixed staging array has no device address");
+    const long long piece = std::min<long long>(apply_piece_qpwfs(c), (long long)(kScratchBytes / per_bytes));
+    return apply_pieces_t<T>(c, first, count, piece, c->scratch_dev, c->scratch_dev, out, 1);
 }
 
 // Kinetic energy of the current state (plane kernel in mode KP_KINETIC).  With
@@ -1912,6 +1940,20 @@ int lise_init(lise_ctx** out, const lise_lattice* lat, int64_t n_qpwf, const lis
     if (e != hipSuccess) return bail(fail(c, LISE_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e)));
     c->lds_limit = prop.sharedMemPerBlock;
     set_all_attrs((int)c->lds_limit);
+    {
+        // the device's own address of the fixed staging array, once per device
+        if (c->device < 0 || c->device >= kMaxDevices)
+            return bail(fail(c, LISE_E_UNSUPPORTED, "device index %d beyond %d", c->device, kMaxDevices));
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_addr[c->device]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return bail(fail(c, LISE_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e)));
+            g_scratch_addr[c->device] = p;
+        }
+        c->scratch_dev = g_scratch_addr[c->device];
+    }
     // plans and twiddles
     std::vector<cpx<double>> tw;
     if (!make_plan(lat->nx, &c->px, &tw) || !make_plan(lat->ny, &c->py, &tw) || !make_plan(lat->nz, &c->pz, &tw))
@@ -2065,6 +2107,13 @@ int lise_apply_h(lise_ctx* c, int64_t first, int64_t count, void* out, int32_t o
     if (first < 0 || count < 1 || first + count > c->M) return fail(c, LISE_E_ARG, "qpwf range out of bounds");
     return c->prec == LISE_FP64 ? apply_h_t<double>(c, first, count, out, out_is_device)
                                 : apply_h_t<float>(c, first, count, out, out_is_device);
+}
+
+int lise_apply_h_noalloc(lise_ctx* c, int64_t first, int64_t count, void* out_device) {
+    if (!c || !out_device) return LISE_E_ARG;
+    if (first < 0 || count < 1 || first + count > c->M) return fail(c, LISE_E_ARG, "qpwf range out of bounds");
+    return c->prec == LISE_FP64 ? apply_h_noalloc_t<double>(c, first, count, out_device)
+                                : apply_h_noalloc_t<float>(c, first, count, out_device);
 }
 
 int lise_startup(lise_ctx* c, double dt) {

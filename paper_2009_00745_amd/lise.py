@@ -18,7 +18,7 @@ ERRORS = {0: "OK", -1: "LISE_E_ARG", -2: "LISE_E_NOMEM", -3: "LISE_E_UNSUPPORTED
           -4: "LISE_E_HIP", -5: "LISE_E_STATE", -6: "LISE_E_NAN"}
 
 # every entry point declared in include/lise.h
-SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_startup",
+SYMBOLS = ["lise_init", "lise_set_qpwf", "lise_get_qpwf", "lise_apply_h", "lise_apply_h_noalloc", "lise_startup",
            "lise_step", "lise_densities", "lise_observables", "lise_get_time", "lise_set_time",
            "lise_set_stream", "lise_set_tuning", "lise_profile", "lise_profile_read",
            "lise_memory", "lise_last_error", "lise_version", "lise_free", "lise_autotune", "lise_coupling",
@@ -83,6 +83,7 @@ def load_library(path=LIB_PATH):
         "lise_set_qpwf": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
         "lise_get_qpwf": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
         "lise_apply_h": ([P, ct.c_int64, ct.c_int64, P, ct.c_int32], ct.c_int),
+        "lise_apply_h_noalloc": ([P, ct.c_int64, ct.c_int64, P], ct.c_int),
         "lise_startup": ([P, ct.c_double], ct.c_int),
         "lise_step": ([P, ct.c_double, ct.c_int64], ct.c_int),
         "lise_densities": ([P, P, P, ct.c_int32], ct.c_int),
@@ -207,6 +208,15 @@ class Context:
             out = np.empty((count, self.C, self.nz, self.ny, self.nx), dtype=np.complex128)
         p, dev = _ptr(out)
         self._check(self.lib.lise_apply_h(self._h, first, count, p, dev), "lise_apply_h")
+        return out
+
+    def apply_h_noalloc(self, first, count, out):
+        """H psi into `out` (a device tensor of count*C*N complex128), staged through the
+        library's fixed per-GPU array: the call allocates nothing."""
+        p, dev = _ptr(out)
+        if not dev:
+            raise ValueError("apply_h_noalloc writes device memory only")
+        self._check(self.lib.lise_apply_h_noalloc(self._h, first, count, p), "lise_apply_h_noalloc")
         return out
 
     def startup(self, dt):

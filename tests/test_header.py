@@ -29,6 +29,7 @@ int main(void) {
         lise_set_qpwf(c, 0, 1, NULL, 0);
         lise_get_qpwf(c, 0, 1, NULL, 0);
         lise_apply_h(c, 0, 1, NULL, 0);
+        lise_apply_h_noalloc(c, 0, 1, NULL);
         lise_startup(c, 0.01);
         lise_step(c, 0.01, 1);
         lise_densities(c, NULL, NULL, 0);
