@@ -8,9 +8,12 @@ density rebuilds).  Inputs are generated on the host, uploaded, and the
 series-expansion start-up plus the warm-up steps run before the timed region.
 
 Prints one JSON line: qpwf-steps/s of the whole job, the roofline of the
-dominant kernel (the plane kernel of the ABM phases, timed with HIP events
-inside the library on its stream), and the CPU oracle timed on a bounded
-sample of the same workload.
+dominant kernel (the plane kernel of ABM phase 1, timed with HIP events inside
+the library on its stream) beside the whole step's fraction, norm and energy
+drift, the CPU oracle timed on a bounded sample of the same workload, and the
+other forms at their own workloads: float32 on the same workload, phase
+removal, the 48^3 float32 vortex workload (16384 qpwfs) and the 64-system
+batch, each float32 form with its density error against float64.
 """
 import argparse
 import json
@@ -87,7 +90,13 @@ def upload(ctx, w, piece=None):
         ctx.set_qpwf(j0, futs.pop(i).result())
 
 
+PROF_CLASSES = ((0, "plane_abm1"), (4, "plane_abm2"), (1, "zaxis"), (2, "fields"))
+
+
 def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
+    """Upload, start up, optionally autotune, warm up, then time `steps` ABM steps.
+    Returns the context, the elapsed seconds, per-class kernel times and the
+    observables at the start of the timed region."""
     import torch
     import paper_2009_00745_amd as lise
     stream = torch.cuda.current_stream().cuda_stream
@@ -106,6 +115,7 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     if warmup:
         ctx.step(w.dt, warmup)
     torch.cuda.synchronize()
+    obs0 = ctx.observables()
     log(f"{w.name}: start-up + {warmup} warm-up steps done")
     if profile:
         ctx.profile(1)
@@ -117,20 +127,58 @@ def run_gpu(w, steps, warmup, tuning=None, profile=True, autotune=False):
     prof = {}
     prof_steps = steps
     if profile:
-        classes = ((0, "plane"), (1, "zaxis"), (2, "fields"))
-        for cls, name in classes:
+        for cls, name in PROF_CLASSES:
             prof[name] = ctx.profile_read(cls)
-        if prof["plane"][0] == 0:
+        if prof["plane_abm1"][0] == 0:
             # graph replays carry no per-launch events: a few eager steps give the kernel times
             prof_steps = 4
             ctx.step(w.dt, prof_steps)
-            for cls, name in classes:
+            for cls, name in PROF_CLASSES:
                 prof[name] = ctx.profile_read(cls)
         ctx.profile(0)
     prof["steps"] = prof_steps
     log(f"{w.name}: {steps} steps in {t2 - t1:.3f}s")
     prof["tuning"] = chosen
+    prof["obs0"] = obs0
     return ctx, t2 - t1, prof
+
+
+def drift(obs0, obs1, steps):
+    """Energy change over the timed steps, relative to |E|, and the norm drift since the
+    qpwfs were set (the library's per-qpwf maximum)."""
+    dE = (obs1["E"] - obs0["E"]) / abs(obs0["E"])
+    return {"E_start": obs0["E"], "E_end": obs1["E"], "E_rel_change": dE, "E_rel_change_per_step": dE / steps,
+            "norm_drift_max": obs1["norm_drift_max"], "norm_drift_mean": obs1["norm_drift_mean"],
+            "N_rel_change": (obs1["N"] - obs0["N"]) / obs0["N"]}
+
+
+def phase_roofline(prof, prof_steps, M, b_alg, rec=None):
+    """Per-kernel bandwidth of the step.  The dominant kernel is the plane kernel of ABM
+    phase 1; each ABM phase is charged half of the step's algorithmic bytes B_alg per
+    qpwf (the unit the step fraction uses), and its design traffic (state arrays it
+    moves, including the z-term scratch) is given beside it."""
+    out = {}
+    arr = b_alg / 16.0                     # one state array of one qpwf
+    design = {"plane_abm1": 10, "plane_abm2": 6, "zaxis": 4}   # arrays per qpwf-step
+    for name in ("plane_abm1", "plane_abm2", "zaxis"):
+        n, ms = prof[name]
+        if n == 0:
+            continue
+        per_launch_q = prof_steps * M / n * (2 if name == "zaxis" else 1)
+        avg_s = ms / n / 1e3
+        d = {"launches": n, "avg_launch_ms": ms / n, "qpwfs_per_launch": per_launch_q,
+             "design_arrays_per_qpwf": design[name] / (2 if name == "zaxis" else 1),
+             "design_GBps": design[name] / (2 if name == "zaxis" else 1) * arr * per_launch_q / avg_s / 1e9}
+        if name != "zaxis":
+            d["alg_bytes_per_launch"] = 0.5 * b_alg * per_launch_q
+            d["alg_GBps"] = d["alg_bytes_per_launch"] / avg_s / 1e9
+            d["frac"] = d["alg_GBps"] * 1e9 / HBM_PEAK
+        if rec:
+            key = {"plane_abm1": "abm1_bytes_per_qpwf", "plane_abm2": "abm2_bytes_per_qpwf",
+                   "zaxis": "kz_bytes_per_qpwf"}[name]
+            d["pmc_traffic_per_launch"] = rec[key] * per_launch_q
+        out[name] = d
+    return out
 
 
 def reduced_error(name, steps, M):
@@ -161,9 +209,43 @@ def reduced_error(name, steps, M):
     return out
 
 
-def run_batched(nsys, steps, warmup, graph=1):
-    """Independent FP32 systems (16^3/20^3/24^3, 512-3072 qpwfs each) advanced together,
-    each on its own forked stream (with its own four-step graph replays when graph = 1)."""
+def run_cfg3(steps, warmup, err_M, err_steps):
+    """48^3 float32 vortex workload at full size (16384 qpwfs, 203 GB of state) timed,
+    plus its float32 density error against float64 on a reduced instance."""
+    import torch
+    w = make_workload("cfg3")
+    ctx, el, prof = run_gpu(w, steps, warmup, None, autotune=False)
+    ps = prof.pop("steps")
+    prof.pop("tuning")
+    obs0 = prof.pop("obs0")
+    obs1 = ctx.observables()
+    mem = ctx.memory()
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    C, N, esz = w.functional.ncomp, w.lattice.n, 8
+    b_alg = 16 * C * N * esz
+    value = w.M * steps / el
+    rec = measured_traffic("cfg3")
+    out = {"workload": f"{w.name}: 48^3 lattice, {w.M} two-component qpwfs, LDA vortex line, float32 state "
+                       "with float64 density/energy sums, dt=0.002",
+           "value": value, "unit": "qpwf-steps/s", "ms_per_step": 1e3 * el / steps, "steps": steps,
+           "dtype": "f32", "device_memory_GiB": mem / 2**30,
+           "step_hbm_frac": value * b_alg / HBM_PEAK, "b_alg_per_qpwf_step": b_alg,
+           "kernels": phase_roofline(prof, ps, w.M, b_alg, rec),
+           "kernel_ms_per_step": {k: ms / ps for k, (n, ms) in prof.items()},
+           "drift": drift(obs0, obs1, steps)}
+    if err_M:
+        out["density_error_vs_fp64"] = reduced_error("cfg3", err_steps, err_M)
+    return out
+
+
+def run_batched(nsys, steps, warmup, err_group=16):
+    """The 64-system workload (16^3/20^3/24^3, 512-3072 float32 qpwfs each): systems of
+    one lattice side share one z-axis and one plane-kernel launch per ABM phase, and
+    four steps replay as one captured graph.  Afterwards the same systems run in
+    float64 (err_group at a time, the float64 state of all 64 would crowd the device)
+    for the same number of steps, and the float32 densities are compared with them."""
     import torch
     import workloads as wl
     import paper_2009_00745_amd as lise
@@ -173,55 +255,111 @@ def run_batched(nsys, steps, warmup, graph=1):
     t0 = time.time()
     for w in systems:
         c = lise.Context(w.lattice, w.M, w.functional, stream=stream)
-        # the systems already overlap one another on their own streams: each
-        # keeps its z kernel on its stream (64 systems: 2.09e6 vs 1.99e6 with
-        # the per-system z stream; 16 systems: equal)
-        c.set_tuning(graph=int(bool(graph)), no_overlap=1)
+        c.set_tuning(no_overlap=1)     # one z-scratch per context (the batch has its own)
         upload(c, w)
         ctxs.append(c)
     log(f"batched: {nsys} systems uploaded in {time.time() - t0:.1f}s")
     b = lise.Batch(ctxs, stream=stream)
     dt = systems[0].dt
-    b.step(dt, 4 * max(1, warmup))       # start-up, graph capture, warm-up replays
+    wsteps = 4 * max(1, (warmup + 3) // 4)
+    b.step(dt, wsteps)                 # start-up, tables, graph capture, warm-up replays
     torch.cuda.synchronize()
+    groups = b.info()
+    obs0 = [c.observables() for c in ctxs]
     nst = 4 * max(1, steps // 4)
     t1 = time.perf_counter()
     b.step(dt, nst)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
+    obs1 = [c.observables() for c in ctxs]
+    # kernel times from eager steps with events (graph replays carry none)
+    b.profile(1)
+    b.step(dt, 4)
+    kt = {name: b.profile_read(cls) for cls, name in ((0, "plane_abm1"), (3, "plane_abm2"), (1, "zaxis"),
+                                                       (2, "fields"))}
+    b.profile(0)
+    total_steps = ctxs[0].time()[1]
+    dens32 = [c.densities() for c in ctxs]
+    b.close()
+    for c in ctxs:
+        c.close()
+    del ctxs
+    torch.cuda.empty_cache()
     qsteps = sum(w.M for w in systems) * nst
     sizes = {}
     for w in systems:
         sizes.setdefault(w.lattice.nx, [0, 0])
         sizes[w.lattice.nx][0] += 1
         sizes[w.lattice.nx][1] += w.M
-    b_alg = sum(w.M * 16 * 2 * w.lattice.n * 8 for w in systems) * nst / el
-    b.close()
-    for c in ctxs:
-        c.close()
-    return {"value": qsteps / el, "unit": "qpwf-steps/s", "systems": nsys, "steps": nst,
-            "ms_per_step": 1e3 * el / nst, "qpwf_total": sum(w.M for w in systems),
+    b_alg_step = sum(w.M * 16 * 2 * w.lattice.n * 8 for w in systems)
+    # float64 reference of every system, err_group systems at a time, same step count
+    errs = []
+    t0 = time.time()
+    for g0 in range(0, nsys, err_group):
+        sub = []
+        for w in systems[g0:g0 + err_group]:
+            w.functional.precision = wl.FP64
+            c = lise.Context(w.lattice, w.M, w.functional, stream=stream)
+            c.set_tuning(no_overlap=1)
+            upload(c, w)
+            sub.append(c)
+        bb = lise.Batch(sub, stream=stream)
+        bb.step(dt, total_steps - 3)
+        for k, c in enumerate(sub):
+            n64, k64 = c.densities()
+            n32, k32 = dens32[g0 + k]
+            errs.append((float(np.linalg.norm(n32 - n64) / np.linalg.norm(n64)),
+                         float(np.linalg.norm(k32 - k64) / np.linalg.norm(k64))))
+        bb.close()
+        for c in sub:
+            c.close()
+        torch.cuda.empty_cache()
+    log(f"batched: float64 reference of {nsys} systems in {time.time() - t0:.1f}s")
+    ms_plane = kt["plane_abm1"][1] / 4
+    dE = [abs(o1["E"] - o0["E"]) / abs(o0["E"]) for o0, o1 in zip(obs0, obs1)]
+    return {"workload": f"cfg5: {nsys} independent float32 systems (lattice 16^3/20^3/24^3, 512-3072 "
+                        "two-component qpwfs each, Delta0 in [0.1, 0.6]), dt=0.002",
+            "value": qsteps / el, "unit": "qpwf-steps/s", "systems": nsys, "steps": nst,
+            "ms_per_step": 1e3 * el / nst, "qpwf_total": sum(w.M for w in systems), "dtype": "f32",
+            "groups": groups[0], "systems_alone": groups[1], "graph": "one captured graph per 4 ABM steps",
             "lattices": {f"{k}^3": {"systems": v[0], "qpwfs": v[1]} for k, v in sorted(sizes.items())},
-            "step_hbm_frac": b_alg / HBM_PEAK}
+            "step_hbm_frac": b_alg_step * nst / el / HBM_PEAK,
+            "kernel_ms_per_step": {k: ms / 4 for k, (n, ms) in kt.items()},
+            "launches_per_step": {k: n / 4 for k, (n, ms) in kt.items()},
+            "plane_abm1_alg_frac": 0.5 * b_alg_step / (ms_plane / 1e3) / HBM_PEAK if ms_plane > 0 else None,
+            "density_error_vs_fp64": {"after_steps": int(total_steps), "systems": len(errs),
+                                      "n_max": max(e[0] for e in errs), "kappa_max": max(e[1] for e in errs),
+                                      "reference": "the same systems stepped in float64 on the GPU"},
+            "drift": {"E_rel_change_max": max(dE), "norm_drift_max": max(o["norm_drift_max"] for o in obs1)}}
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kp_fast_fp64_32c_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
+# PMC traffic summaries: workload key -> file, each with one TRAFFIC_JSON line
+TRAFFIC_FILES = {"cfg2": "kp_fast_fp64_32c_traffic.md", "cfg2_fp32": "kp_fast_fp32_32c_traffic.md",
+                 "cfg3": "kp_fast_fp32_48c_traffic.md"}
 KERNEL_SOURCES = ("paper_2009_00745_amd/csrc/lise_device.hpp", "paper_2009_00745_amd/csrc/lise_fast.hpp")
 
 
-def measured_traffic():
-    """Per-qpwf HBM traffic of the ABM plane kernels from the committed PMC summary, or None
-    when the kernel sources changed since the counters were taken."""
+def source_hash():
     import hashlib
-    try:
-        line = [ln for ln in open(TRAFFIC_PROFILE) if ln.startswith("TRAFFIC_JSON ")][0]
-    except (OSError, IndexError):
-        return None
-    rec = json.loads(line[len("TRAFFIC_JSON "):])
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return rec if h.hexdigest()[:16] == rec["source_hash"] else None
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key="cfg2"):
+    """Per-qpwf HBM traffic of the ABM kernels from the committed PMC summary of the
+    workload, or None when there is none or the kernel sources changed since the
+    counters were taken."""
+    if key not in TRAFFIC_FILES:
+        return None
+    try:
+        line = [ln for ln in open(os.path.join(PROFILES, TRAFFIC_FILES[key])) if ln.startswith("TRAFFIC_JSON ")][0]
+    except (OSError, IndexError):
+        return None
+    rec = json.loads(line[len("TRAFFIC_JSON "):])
+    return rec if rec["source_hash"] == source_hash() else None
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=3):
@@ -292,11 +430,15 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-phase", action="store_true",
                     help="skip the variant with the trivial phase removed (Eq. sp_en)")
-    ap.add_argument("--batched", type=int, default=16,
-                    help="number of independent systems in the batched variant (0 = skip; 64 = full workload)")
+    ap.add_argument("--batched", type=int, default=64,
+                    help="number of independent systems in the batched form (0 = skip; 64 = the full workload)")
+    ap.add_argument("--cfg3", type=int, default=1,
+                    help="1 = also time the 48^3 float32 vortex workload (16384 qpwfs); 0 = skip")
+    ap.add_argument("--cfg3-error-M", type=int, default=2048,
+                    help="qpwfs of the reduced 48^3 instance on which float32 is compared with float64")
     ap.add_argument("--reduced-error", type=int, default=0, metavar="M",
-                    help="cfg3/cfg4: also measure the float32 density error against float64 on the same "
-                         "workload with M qpwfs (4096 for cfg3, 1024 for cfg4 fit in float64)")
+                    help="cfg3/cfg4 as the main workload: also measure the float32 density error against "
+                         "float64 on the same workload with M qpwfs")
     ap.add_argument("--reduced-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -307,10 +449,6 @@ def main():
               "multi-GPU sharding over qpwfs is a design note, not a run (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
-    # the batched leg runs one stream per system; HIP maps streams onto this many
-    # hardware queues (default 4), read when HIP initialises
-    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
-        os.environ["GPU_MAX_HW_QUEUES"] = "16"
     start_pool()
     import torch
     if not torch.cuda.is_available():
@@ -343,26 +481,25 @@ def main():
     ctx, elapsed, prof = run_gpu(w, args.steps, args.warmup, tuning, autotune=autotune)
     chosen = prof.pop("tuning")
     prof_steps = prof.pop("steps")
+    obs0 = prof.pop("obs0")
     value = w.M * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
     b_alg = 16 * C * N * esz                      # compulsory state bytes per qpwf-step
-    n_plane, ms_plane = prof["plane"]
-    # the plane kernel moves the ABM state: phase 1 reads 6 and writes 1 state array,
-    # phase 2 reads 7 and writes 2, per qpwf (the split of the 16-array step minimum)
-    alg_bytes_total = prof_steps * w.M * b_alg
-    avg_launch_s = ms_plane / n_plane / 1e3
-    achieved = (alg_bytes_total / n_plane) / avg_launch_s
-    traffic = None
-    rec = measured_traffic() if (w.lattice.nx, w.lattice.ny, w.lattice.nz, C, esz) == (32, 32, 32, 2, 16) else None
-    if rec:
-        qpwf_per_launch = prof_steps * w.M * 2 / n_plane
-        traffic = 0.5 * (rec["abm1_bytes_per_qpwf"] + rec["abm2_bytes_per_qpwf"]) * qpwf_per_launch
-    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "measured_copy_GBps": copy_bandwidth() / 1e9,
-                "kernel": "plane kernel, ABM phases (kp_fast on 8..64 sides)", "launches": n_plane,
-                "avg_launch_ms": ms_plane / n_plane,
-                "alg_bytes_per_launch": alg_bytes_total / n_plane}
+    step_frac = value * b_alg / HBM_PEAK
+    key = args.workload if args.workload in TRAFFIC_FILES else None
+    rec = measured_traffic(key) if key and args.M is None else None
+    kernels = phase_roofline(prof, prof_steps, w.M, b_alg, rec)
+    dom = kernels["plane_abm1"]
+    roofline = {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": dom["frac"],
+                "traffic": dom.get("pmc_traffic_per_launch"),
+                "kernel": "plane kernel of ABM phase 1 (kp_fast, mode KP_ABM1)",
+                "launches": dom["launches"], "avg_launch_ms": dom["avg_launch_ms"],
+                "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+                "alg_unit": "B_alg / 2 per qpwf of the launch (half of the step's 16 state arrays)",
+                "step_frac": step_frac,
+                "phases": kernels,
+                "measured_copy_GBps": copy_bandwidth() / 1e9}
     if prof_steps != args.steps:
         roofline["kernel_times_from"] = (f"{prof_steps} eager steps after the timed graph replays "
                                          "(replays carry no per-launch events)")
@@ -376,6 +513,10 @@ def main():
     t_now, s_now = ctx.time()
     n64, k64 = ctx.densities()
     obs = ctx.observables()
+    drift_main = drift(obs0, obs, args.steps)
+    if w.functional.ext_A != 0.0:
+        drift_main["note"] = ("the external well is ramped on over the first 100 steps of the run: E changes "
+                              "by the work of the time-dependent field, not by integration error alone")
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -387,21 +528,28 @@ def main():
                                       autotune=autotune)
         chosen32 = prof32.pop("tuning")
         ps32 = prof32.pop("steps")
+        o32 = prof32.pop("obs0")
         n32, k32 = ctx32.densities()
         t32, s32 = ctx32.time()
+        o32b = ctx32.observables()
         ctx32.close()
         same = s32 == s_now    # densities are compared after equal step counts only
+        val32 = w32.M * args.steps / el32
+        b32 = 16 * C * N * 8
         variants["fp32_same_workload"] = {
-            "value": w32.M * args.steps / el32, "unit": "qpwf-steps/s",
+            "value": val32, "unit": "qpwf-steps/s",
             "ms_per_step": 1e3 * el32 / args.steps,
             "kernel_ms_per_step": {k: ms / ps32 for k, (n, ms) in prof32.items()},
-            "speedup_vs_fp64": (w32.M * args.steps / el32) / value,
+            "kernels": phase_roofline(prof32, ps32, w32.M, b32,
+                                      measured_traffic("cfg2_fp32") if args.M is None else None),
+            "speedup_vs_fp64": val32 / value,
             "density_rel_l2_vs_fp64": {
                 "n": float(np.linalg.norm(n32 - n64) / np.linalg.norm(n64)),
                 "kappa": float(np.linalg.norm(k32 - k64) / np.linalg.norm(k64))} if same else None,
             "after_steps": int(s32),
             "tuning": chosen32,
-            "step_hbm_frac": (w32.M * args.steps / el32) * 16 * C * N * 8 / HBM_PEAK}
+            "drift": drift(o32, o32b, args.steps),
+            "step_hbm_frac": val32 * b32 / HBM_PEAK}
 
     if not args.no_phase and args.workload == "cfg2":
         wp = make_workload("cfg2", M=args.M)
@@ -410,6 +558,7 @@ def main():
                                    autotune=autotune)
         chosenp = profp.pop("tuning")
         psp = profp.pop("steps")
+        profp.pop("obs0")
         n_p, k_p = ctxp.densities()
         tp, sp = ctxp.time()
         ctxp.close()
@@ -427,6 +576,10 @@ def main():
 
     if args.reduced_error and args.workload in ("cfg3", "cfg4", "cfg4_fp32"):
         variants["reduced_error"] = reduced_error(args.workload[:4], args.reduced_steps, args.reduced_error)
+
+    if args.cfg3 and args.workload == "cfg2":
+        variants["cfg3_fp32_48c_m16384"] = run_cfg3(args.steps // 2, args.warmup, args.cfg3_error_M,
+                                                    args.reduced_steps)
 
     if args.batched and args.workload == "cfg2":
         variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
@@ -447,10 +600,11 @@ def main():
                    "ncomp": C, "dt": w.dt, "tuning": tuning or "default"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "step_hbm_frac": value * b_alg / HBM_PEAK,
+        "step_hbm_frac": step_frac,
         "b_alg_per_qpwf_step": b_alg,
         "kernel_ms_per_step": breakdown,
         "observables": {"t": t_now, "N": obs["N"], "E": obs["E"], "norm_drift_max": obs["norm_drift_max"]},
+        "drift": drift_main,
         "variants": variants,
         "host": platform.node(),
     }

@@ -48,6 +48,10 @@ int main(void) {
         lise_load(c, "x");
         lise_batch_create(&b, 1, &c, NULL);
         lise_batch_step(b, 0.01, 1);
+        lise_batch_set_graph(b, 1);
+        lise_batch_info(b, NULL, NULL);
+        lise_batch_profile(b, 1);
+        lise_batch_profile_read(b, 0, &n, &ms);
         (void)lise_batch_last_error(b);
         lise_batch_free(b);
         (void)lise_last_error(c);
