@@ -240,7 +240,7 @@ def run_cfg3(steps, warmup, err_M, err_steps):
     return out
 
 
-def run_batched(nsys, steps, warmup, err_group=16):
+def run_batched(nsys, steps, warmup, err_group=16, with_error=True):
     """The 64-system workload (16^3/20^3/24^3, 512-3072 float32 qpwfs each): systems of
     one lattice side share one z-axis and one plane-kernel launch per ABM phase, and
     four steps replay as one captured graph.  Afterwards the same systems run in
@@ -295,7 +295,7 @@ def run_batched(nsys, steps, warmup, err_group=16):
     # float64 reference of every system, err_group systems at a time, same step count
     errs = []
     t0 = time.time()
-    for g0 in range(0, nsys, err_group):
+    for g0 in range(0, nsys if with_error else 0, err_group):
         sub = []
         for w in systems[g0:g0 + err_group]:
             w.functional.precision = wl.FP64
@@ -317,6 +317,17 @@ def run_batched(nsys, steps, warmup, err_group=16):
     log(f"batched: float64 reference of {nsys} systems in {time.time() - t0:.1f}s")
     ms_plane = kt["plane_abm1"][1] / 4
     dE = [abs(o1["E"] - o0["E"]) / abs(o0["E"]) for o0, o1 in zip(obs0, obs1)]
+    rec = measured_traffic("cfg5")
+    traffic = None
+    if rec:
+        per = 0.0
+        for w in systems:
+            n = w.lattice.nx
+            per += w.M * (rec.get(f"kp_fast_batch<float, {n}, 1>", float("nan")) +
+                          rec.get(f"kp_fast_batch<float, {n}, 2>", float("nan")) +
+                          2 * rec.get(f"kz_fast_batch<float, {n}, 1, false>", float("nan")))
+        traffic = {"bytes_per_step": per, "vs_alg_bytes": per / b_alg_step,
+                   "GBps_over_step": per * nst / el / 1e9}
     return {"workload": f"cfg5: {nsys} independent float32 systems (lattice 16^3/20^3/24^3, 512-3072 "
                         "two-component qpwfs each, Delta0 in [0.1, 0.6]), dt=0.002",
             "value": qsteps / el, "unit": "qpwf-steps/s", "systems": nsys, "steps": nst,
@@ -329,14 +340,16 @@ def run_batched(nsys, steps, warmup, err_group=16):
             "plane_abm1_alg_frac": 0.5 * b_alg_step / (ms_plane / 1e3) / HBM_PEAK if ms_plane > 0 else None,
             "density_error_vs_fp64": {"after_steps": int(total_steps), "systems": len(errs),
                                       "n_max": max(e[0] for e in errs), "kappa_max": max(e[1] for e in errs),
-                                      "reference": "the same systems stepped in float64 on the GPU"},
+                                      "reference": "the same systems stepped in float64 on the GPU"} if errs else None,
+            "pmc_traffic": traffic,
             "drift": {"E_rel_change_max": max(dE), "norm_drift_max": max(o["norm_drift_max"] for o in obs1)}}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
 # PMC traffic summaries: workload key -> file, each with one TRAFFIC_JSON line
 TRAFFIC_FILES = {"cfg2": "kp_fast_fp64_32c_traffic.md", "cfg2_fp32": "kp_fast_fp32_32c_traffic.md",
-                 "cfg3": "kp_fast_fp32_48c_traffic.md"}
+                 "cfg3": "kp_fast_fp32_48c_traffic.md", "cfg4": "kp_mfma_64c4_traffic.md",
+                 "cfg4_fp32": "kp_fast_fp32_64c4_traffic.md", "cfg5": "kp_fast_batch_cfg5_traffic.md"}
 KERNEL_SOURCES = ("paper_2009_00745_amd/csrc/lise_device.hpp", "paper_2009_00745_amd/csrc/lise_fast.hpp")
 
 
@@ -432,6 +445,8 @@ def main():
                     help="skip the variant with the trivial phase removed (Eq. sp_en)")
     ap.add_argument("--batched", type=int, default=64,
                     help="number of independent systems in the batched form (0 = skip; 64 = the full workload)")
+    ap.add_argument("--batch-no-error", action="store_true",
+                    help="skip the float64 reference run of the batched systems (profiling runs)")
     ap.add_argument("--cfg3", type=int, default=1,
                     help="1 = also time the 48^3 float32 vortex workload (16384 qpwfs); 0 = skip")
     ap.add_argument("--cfg3-error-M", type=int, default=2048,
@@ -487,7 +502,7 @@ def main():
     b_alg = 16 * C * N * esz                      # compulsory state bytes per qpwf-step
     step_frac = value * b_alg / HBM_PEAK
     key = args.workload if args.workload in TRAFFIC_FILES else None
-    rec = measured_traffic(key) if key and args.M is None else None
+    rec = measured_traffic(key) if key else None
     kernels = phase_roofline(prof, prof_steps, w.M, b_alg, rec)
     dom = kernels["plane_abm1"]
     roofline = {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -540,8 +555,7 @@ def main():
             "value": val32, "unit": "qpwf-steps/s",
             "ms_per_step": 1e3 * el32 / args.steps,
             "kernel_ms_per_step": {k: ms / ps32 for k, (n, ms) in prof32.items()},
-            "kernels": phase_roofline(prof32, ps32, w32.M, b32,
-                                      measured_traffic("cfg2_fp32") if args.M is None else None),
+            "kernels": phase_roofline(prof32, ps32, w32.M, b32, measured_traffic("cfg2_fp32")),
             "speedup_vs_fp64": val32 / value,
             "density_rel_l2_vs_fp64": {
                 "n": float(np.linalg.norm(n32 - n64) / np.linalg.norm(n64)),
@@ -582,7 +596,8 @@ def main():
                                                     args.reduced_steps)
 
     if args.batched and args.workload == "cfg2":
-        variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup)
+        variants["batched_fp32"] = run_batched(args.batched, args.steps, args.warmup,
+                                               with_error=not args.batch_no_error)
 
     cpu = None
     if not args.no_cpu:

@@ -54,3 +54,19 @@ def test_traffic_record_from_profile():
     assert 6 * mib <= stored["abm2_bytes_per_qpwf"] < 6.5 * mib
     assert 2 * mib <= stored["kz_bytes_per_qpwf"] < 2.05 * mib
     assert rec is None or rec == stored
+
+
+def test_every_traffic_file_holds_a_record():
+    """Each form's PMC summary named in bench.TRAFFIC_FILES exists, gives its rocprofv3
+    commands and one TRAFFIC_JSON line with per-qpwf bytes for every kernel it covers."""
+    import bench
+    for key, name in bench.TRAFFIC_FILES.items():
+        path = os.path.join(ROOT, "profiles", name)
+        text = open(path).read()
+        assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text, name
+        lines = [l for l in text.splitlines() if l.startswith("TRAFFIC_JSON ")]
+        assert len(lines) == 1, name
+        rec = json.loads(lines[0].split(" ", 1)[1])
+        assert len(rec["source_hash"]) == 16
+        vals = [v for k, v in rec.items() if k != "source_hash"]
+        assert vals and all(v > 0 for v in vals), name
