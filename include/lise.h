@@ -152,7 +152,8 @@ typedef struct {
  *                z-term scratch (chunk x C x N elements, a second one when
  *                the z kernel overlaps; default: about 1 GiB of qpwfs)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
- *                (sets the number of density partial sums; default 32)
+ *                (sets the number of density partial sums; 0 = default:
+ *                32, or 4 on the single-pass path below)
  *   fused      : whole-cube kernel (one pass, the cube in LDS): 1 = whenever
  *                the cube fits in LDS; 0 = only where the register-FFT
  *                kernels below do not cover the lattice; -1 = never (always
@@ -165,7 +166,24 @@ typedef struct {
  *                (two z-scratch buffers, ordered by events)
  *   graph      : 1 = lise_step captures four ABM steps (one period of the
  *                buffer ring) in a HIP graph and replays it; results are
- *                bit-identical to eager stepping */
+ *                bit-identical to eager stepping
+ *   single_pass: the ABM phases of cubic lattices of side 8 or 16 (and 20 in
+ *                LISE_FP32) without phase removal run one kernel per phase
+ *                that holds the whole component pair of a qpwf in LDS and
+ *                applies the kinetic term as a 3D transform, instead of the
+ *                z-axis kernel plus the plane kernel (no z-term scratch: 14
+ *                state arrays per step instead of 20).  1 = wherever
+ *                available, 0 = default (side 8 only: there it measured
+ *                faster, at 16 and 20 slower), -1 = never; start-up,
+ *                lise_apply_h and the observables keep the two kernels.
+ *                jgroup's default is 4 qpwfs per workgroup on this path (32
+ *                on the others).  lise_autotune times both paths.
+ *   z_lanes    : lanes that share one z-column in the register-FFT z-axis
+ *                kernel: 1 (the column in one thread's registers), 2 or 4
+ *                (each lane nz/L points, exchanges across lanes); 0 =
+ *                default (1); a value that does not divide nz into >= 2
+ *                points per lane falls back to 1.  Errors: ARG for other
+ *                values. */
 typedef struct {
     int32_t chunk_qpwf;
     int32_t jgroup;
@@ -173,6 +191,8 @@ typedef struct {
     int32_t generic;
     int32_t no_overlap;
     int32_t graph;
+    int32_t single_pass;
+    int32_t z_lanes;
 } lise_tuning;
 
 /* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the
@@ -270,12 +290,14 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
 int lise_profile(lise_ctx *c, int32_t enable);
 int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 
-/* Timed search over launch tuning (chunk size, qpwfs per plane workgroup 8/16/32/64,
- * z-kernel overlap) for this system: each candidate runs one untimed and
- * `trial_steps` timed ABM steps with step size dt on the live state (the
- * state advances; results change only in rounding); the three fastest run
- * again over 2 * trial_steps and the fastest of that round is kept and
- * written to *chosen (may be NULL).  Runs the start-up first if needed.
+/* Timed search over launch tuning for this system: chunk size, qpwfs per
+ * plane workgroup 8/16/32/64 and z-kernel overlap on the two-kernel path,
+ * and 2/4/8/16 qpwfs per workgroup on the single-pass path where it applies;
+ * each candidate runs one untimed and `trial_steps` timed ABM steps with
+ * step size dt on the live state (the state advances; results change only
+ * in rounding).  The three fastest run again over 2 * trial_steps, each also
+ * with 2 and 4 lanes per z-column where the z kernel runs, and the fastest
+ * of that round is kept and written to *chosen (may be NULL).  Runs the start-up first if needed.
  * Errors: ARG, STATE, HIP, NAN. */
 int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);
 

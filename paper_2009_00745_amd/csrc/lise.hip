@@ -18,6 +18,7 @@
 #include "lise_plan.hpp"
 #include "lise_fast.hpp"
 #include "lise_mfma.hpp"
+#include "lise_cube.hpp"
 #include <type_traits>
 
 using namespace lise;
@@ -31,6 +32,8 @@ namespace {
 constexpr int kThreads = 256;
 const char* kVersion = "lise-mi355x 0.1 (gfx950)";
 constexpr int kBatchPeriod = 4;   // ABM steps after which the buffer ring repeats
+constexpr int kPlaneJg = 32;      // default qpwfs per workgroup row of the plane kernels
+constexpr int kCubeJg = 4;        // ... of the single-pass kernel (one workgroup holds a whole qpwf)
 
 // Staging memory of lise_apply_h_noalloc: one fixed array per GPU, held until
 // the process ends, shared by every context on that GPU.  Host code never
@@ -103,6 +106,11 @@ struct lise_ctx {
 
     // tuning
     int chunk = 0, jg = 32, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
+    int jg_user = 0;            // jgroup the caller set (0: the path's default)
+    int single_pass = 0;        // -1 never, 0 auto, 1 prefer the single-pass ABM kernel
+    int zl_user = 0;            // lanes per z-column the caller set (0: default)
+    int zl = 1;                 // lanes per z-column of the register-FFT z kernel (1, 2 or 4)
+    bool cube = false;          // ABM phases by the single-pass kernel (lise_cube.hpp)
     bool stream_hint = false;   // z kernel takes nontemporal hints (as the plane kernel does)
     bool fused = false;
     int zb = 1, yb = 1, ppt = 4;
@@ -250,6 +258,12 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if constexpr (cube_side((int)sizeof(T), NS)) {
+        (void)hipFuncSetAttribute((const void*)kc_fast<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)kc_fast<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
 }
 
 template <typename T>
@@ -291,6 +305,14 @@ void set_all_attrs(int lim) {
     set_mfma_attrs<64>(lim);
 }
 
+// Whether the single-pass ABM kernel covers the lattice (after the
+// register-FFT flags are set).
+bool cube_eligible(const lise_ctx* c) {
+    const int n = c->lat.nx;
+    return c->fast_xy && c->fast_z && n == c->lat.ny && n == c->lat.nz && cube_side((int)c->esz / 2, n) &&
+           cube_lds_of((int)c->esz / 2, n) <= c->lds_limit && !c->remove_phase;
+}
+
 // Choose launch geometry and (re)allocate scratch for the current tuning.
 int configure(lise_ctx* c) {
     c->config_version += 1;
@@ -323,6 +345,12 @@ int configure(lise_ctx* c) {
                  fast_kp_lds(c) <= c->lds_limit && c->tw_full_xy >= 0;
     c->fast_z = !c->fused && !c->generic && fast_side(nz) && c->tw_full_z >= 0;
     if (c->fast_xy || c->mfma_xy) c->zb = 1;
+    c->zl = (c->zl_user > 0 && kz_lanes_valid(nz, c->zl_user)) ? c->zl_user : kz_lanes_of(nz);
+    // single-pass ABM kernel: the whole pair of component cubes in LDS; by
+    // default only on 8^3 (measured 2.4x faster there, 2x slower than the
+    // two kernels at 16^3 and 20^3)
+    c->cube = cube_eligible(c) && (c->single_pass > 0 || (c->single_pass == 0 && nx == 8));
+    c->jg = c->jg_user > 0 ? c->jg_user : (c->cube ? kCubeJg : kPlaneJg);
     c->stream_hint = c->mfma_xy || (c->fast_xy && plane_stream_hint_of(c->esz / 2, nx));
     // the generic LDS kernels must fit where they are the ones that run
     if (!c->fused && !c->fast_xy && !c->mfma_xy && kp_lds_bytes(c, c->zb) > c->lds_limit)
@@ -373,7 +401,7 @@ int configure(lise_ctx* c) {
         }
         if (!c->eta) CHK(dalloc(c, reinterpret_cast<void**>(&c->eta), (size_t)c->M * sizeof(double)));
         if (c->fast_xy && c->fast_z) {
-            const long long nez = c->chunk * (long long)c->C * nxy * kz_lanes_of(nz);
+            const long long nez = c->chunk * (long long)c->C * nxy * c->zl;
             if (c->ez_cap < nez) {
                 for (int b = 0; b < 2; ++b) {
                     dfree(reinterpret_cast<void**>(&c->ez_part[b]));
@@ -519,23 +547,32 @@ int launch_kp_t(lise_ctx* c, KPArgs<T>& a, long long j0, int k, int cls) {
 // nt: nontemporal hints on the column loads and scratch stores, taken where
 // the plane kernel of the lattice takes them (whole-line plane rows; small
 // lattices keep the default cache policy throughout)
+template <typename T, int NZ, bool NT, int L>
+void launch_kz_fast_l(const KZFastArgs<T>& f, hipStream_t st) {
+    if constexpr (kz_lanes_valid(NZ, L)) {
+        const long long threads = f.ncols * L;
+        dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
+        if constexpr (L > 1)
+            hipLaunchKernelGGL((kz_lanes_kernel<T, NZ, L, NT>), grid, dim3(kThreads), 0, st, f);
+        else
+            hipLaunchKernelGGL((kz_fast<T, NZ, NT>), grid, dim3(kThreads), 0, st, f);
+    }
+}
+
+// zl: lanes per column (1, 2 or 4; configure keeps only valid values)
 template <typename T, int NZ, bool NT>
-void launch_kz_fast_nt(const KZFastArgs<T>& f, hipStream_t st) {
-    constexpr int L = kz_lanes<NZ>();
-    const long long threads = f.ncols * L;
-    dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
-    if constexpr (L > 1)
-        hipLaunchKernelGGL((kz_lanes_kernel<T, NZ, L, NT>), grid, dim3(kThreads), 0, st, f);
-    else
-        hipLaunchKernelGGL((kz_fast<T, NZ, NT>), grid, dim3(kThreads), 0, st, f);
+void launch_kz_fast_nt(const KZFastArgs<T>& f, hipStream_t st, int zl) {
+    if (zl == 4) launch_kz_fast_l<T, NZ, NT, 4>(f, st);
+    else if (zl == 2) launch_kz_fast_l<T, NZ, NT, 2>(f, st);
+    else launch_kz_fast_l<T, NZ, NT, 1>(f, st);
 }
 
 template <typename T, int NZ>
-void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st, bool nt) {
+void launch_kz_fast_n(const KZFastArgs<T>& f, hipStream_t st, bool nt, int zl) {
     if (nt)
-        launch_kz_fast_nt<T, NZ, true>(f, st);
+        launch_kz_fast_nt<T, NZ, true>(f, st, zl);
     else
-        launch_kz_fast_nt<T, NZ, false>(f, st);
+        launch_kz_fast_nt<T, NZ, false>(f, st, zl);
 }
 
 template <typename T>
@@ -558,13 +595,13 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
         hipEvent_t ev;
         prof_begin(c, 1, &ev, st);
         switch (c->lat.nz) {
-            case 8: launch_kz_fast_n<T, 8>(f, st, c->stream_hint); break;
-            case 16: launch_kz_fast_n<T, 16>(f, st, c->stream_hint); break;
-            case 20: launch_kz_fast_n<T, 20>(f, st, c->stream_hint); break;
-            case 24: launch_kz_fast_n<T, 24>(f, st, c->stream_hint); break;
-            case 32: launch_kz_fast_n<T, 32>(f, st, c->stream_hint); break;
-            case 48: launch_kz_fast_n<T, 48>(f, st, c->stream_hint); break;
-            default: launch_kz_fast_n<T, 64>(f, st, c->stream_hint); break;
+            case 8: launch_kz_fast_n<T, 8>(f, st, c->stream_hint, c->zl); break;
+            case 16: launch_kz_fast_n<T, 16>(f, st, c->stream_hint, c->zl); break;
+            case 20: launch_kz_fast_n<T, 20>(f, st, c->stream_hint, c->zl); break;
+            case 24: launch_kz_fast_n<T, 24>(f, st, c->stream_hint, c->zl); break;
+            case 32: launch_kz_fast_n<T, 32>(f, st, c->stream_hint, c->zl); break;
+            case 48: launch_kz_fast_n<T, 48>(f, st, c->stream_hint, c->zl); break;
+            default: launch_kz_fast_n<T, 64>(f, st, c->stream_hint, c->zl); break;
         }
         prof_end(c, 1, ev, st);
         return check_launch(c, "kz_fast");
@@ -591,6 +628,44 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
     hipLaunchKernelGGL((kz_kernel<T>), grid, dim3(kThreads), lds, st, a);
     prof_end(c, 1, ev, st);
     return check_launch(c, "kz_kernel");
+}
+
+// The single-pass ABM kernel (lise_cube.hpp): the kinetic factors carry
+// 1 / N^3 of the 3D round trip.
+template <typename T, int N, int MODE>
+void launch_kc_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
+    if constexpr (cube_side((int)sizeof(T), N)) {
+        hipLaunchKernelGGL((kc_fast<T, N, MODE>), grid, dim3(cube_threads_of((int)sizeof(T), N)),
+                           cube_lds_of((int)sizeof(T), N), c->stream, a,
+                           reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
+    }
+}
+
+template <typename T>
+void cube_factors(const lise_ctx* c, KPArgs<T>& a) {
+    const double pi = 3.14159265358979323846;
+    const double n3 = (double)c->N;
+    const double lx = c->lat.nx * c->lat.a, ly = c->lat.ny * c->lat.a, lz = c->lat.nz * c->lat.a;
+    a.cx = T(2.0 * pi * pi / (lx * lx) / n3);
+    a.cy = T(2.0 * pi * pi / (ly * ly) / n3);
+    a.cz = T(2.0 * pi * pi / (lz * lz) / n3);
+}
+
+template <typename T, int MODE>
+int launch_kc_t(lise_ctx* c, KPArgs<T> a, long long j0, int k, int cls) {
+    a.j0 = j0;
+    a.kcount = k;
+    cube_factors<T>(c, a);
+    dim3 grid(1, (unsigned)((k + a.jg - 1) / a.jg));
+    hipEvent_t ev;
+    prof_begin(c, cls, &ev);
+    switch (c->lat.nx) {
+        case 8: launch_kc_n<T, 8, MODE>(c, a, grid); break;
+        case 16: launch_kc_n<T, 16, MODE>(c, a, grid); break;
+        default: launch_kc_n<T, 20, MODE>(c, a, grid); break;
+    }
+    prof_end(c, cls, ev);
+    return check_launch(c, "kc_fast");
 }
 
 // One Hamiltonian application over all qpwfs [first, first+count) in chunks:
@@ -622,7 +697,7 @@ int eta_pass_t(lise_ctx* c, const KPArgs<T>& main, long long j0, int k, const do
     if (ez) {
         e.jg = kEtaJg;
         CHK((launch_kp_t<T, KP_ETAXY>(c, e, j0, k, 3)));
-        const long long nez = (long long)c->C * c->lat.nx * c->lat.ny * kz_lanes_of(c->lat.nz);
+        const long long nez = (long long)c->C * c->lat.nx * c->lat.ny * c->zl;
         hipLaunchKernelGGL(eta_reduce2_kernel, dim3((unsigned)k), dim3(256), 0, c->stream, c->eta_part,
                            (int)etaxy_parts(c), ez, nez, a3, c->eta + j0);
         return check_launch(c, "eta_reduce2_kernel");
@@ -641,6 +716,17 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
     if (!c->remove_phase) eta_op = 0;
     a.eta = eta_op ? c->eta : nullptr;
     const int dens = a.dens_src;
+    if constexpr (MODE == KP_ABM1 || MODE == KP_ABM2) {
+        if (c->cube && !a.eta) {   // one pass per chunk, no z-term
+            for (long long j0 = first, ci = 0; j0 < first + count; j0 += c->chunk, ++ci) {
+                const int k = (int)std::min<long long>(c->chunk, first + count - j0);
+                a.G = nullptr;
+                a.accumulate = (dens && ci > 0) ? 1 : 0;
+                CHK((launch_kc_t<T, MODE>(c, a, j0, k, cls)));
+            }
+            return LISE_OK;
+        }
+    }
     const bool ov = c->overlap && !c->fused && c->s2;
     if (ov) {
         HIPCHK(c, hipEventRecord(c->ev_start, c->stream));
@@ -1365,6 +1451,8 @@ int valid_dim(int n) {
 struct BatchGroup {
     int prec = LISE_FP64;
     int nx = 0, nz = 0;
+    bool cube = false;             // single-pass kernel, no z-axis launch or z-scratch
+    int zl = 1;                    // lanes per z-column
     std::vector<int> sys;          // indices into lise_batch::sys
     std::vector<size_t> goff;      // byte offset of each system's region of the z-scratch
     size_t gbytes = 0;             // z-scratch of the group: sum of M * C * N elements
@@ -1464,7 +1552,7 @@ void batch_fill_group(lise_batch* b, const BatchGroup& g, std::vector<unsigned c
         const lise_ctx* c = b->sys[g.sys[i]];
         rows[i + 1] = rows[i] + (int)((c->M + c->jg - 1) / c->jg);
         const long long ncols = c->M * c->C * (long long)c->lat.nx * c->lat.ny;
-        blks[i + 1] = blks[i] + (ncols * kz_lanes_of(c->lat.nz) + kThreads - 1) / kThreads;
+        blks[i + 1] = blks[i] + (ncols * c->zl + kThreads - 1) / kThreads;
     }
     std::memcpy(h.data() + g.off_rows, rows.data(), rows.size() * sizeof(int));
     std::memcpy(h.data() + g.off_blks, blks.data(), blks.size() * sizeof(long long));
@@ -1476,11 +1564,12 @@ void batch_fill_group(lise_batch* b, const BatchGroup& g, std::vector<unsigned c
                 batch_ring(b, g.sys[i], st, &iy, &dn);
                 const int d0 = 2 + dn, d1 = 2 + (dn + 3) % 4, d2 = 2 + (dn + 2) % 4, d3 = 2 + (dn + 1) % 4;
                 const int yn = iy, ym1 = 1 - iy;
-                cpx<T>* Gs = reinterpret_cast<cpx<T>*>(static_cast<char*>(b->G) + g.goff[i]);
+                cpx<T>* Gs = g.cube ? nullptr : reinterpret_cast<cpx<T>*>(static_cast<char*>(b->G) + g.goff[i]);
                 KPArgs<T> a = kp_base<T>(c);
                 a.j0 = 0;
                 a.kcount = (int)c->M;
-                a.G = Gs;
+                a.G = g.cube ? nullptr : Gs;
+                if (g.cube) cube_factors<T>(c, a);
                 a.dt = dt;
                 a.dens_src = 1;
                 a.accumulate = 0;
@@ -1541,20 +1630,23 @@ int batch_build(lise_batch* b, double dt) {
         }
         BatchGroup* g = nullptr;
         for (auto& x : b->groups)
-            if (x.prec == c->prec && x.nx == c->lat.nx && x.nz == c->lat.nz) g = &x;
+            if (x.prec == c->prec && x.nx == c->lat.nx && x.nz == c->lat.nz && x.cube == c->cube && x.zl == c->zl)
+                g = &x;
         if (!g) {
             b->groups.emplace_back();
             g = &b->groups.back();
             g->prec = c->prec;
             g->nx = c->lat.nx;
             g->nz = c->lat.nz;
+            g->cube = c->cube;
+            g->zl = c->zl;
         }
         g->sys.push_back(i);
         g->goff.push_back(g->gbytes);   // systems of one group may differ in C
-        g->gbytes += (size_t)c->M * c->per * c->esz;
+        if (!c->cube) g->gbytes += (size_t)c->M * c->per * c->esz;
         g->qpwfs += c->M;
         g->rows += (int)((c->M + c->jg - 1) / c->jg);
-        g->zblocks += (c->M * c->C * (long long)c->lat.nx * c->lat.ny * kz_lanes_of(c->lat.nz) + kThreads - 1) / kThreads;
+        g->zblocks += (c->M * c->C * (long long)c->lat.nx * c->lat.ny * c->zl + kThreads - 1) / kThreads;
         b->grouped.push_back(i);
     }
     if (b->grouped.empty()) return LISE_OK;
@@ -1687,12 +1779,33 @@ void launch_kp_batch_n(lise_batch* b, const BatchGroup& g, int st, const cpx<T>*
                        rows, (int)g.sys.size(), twN);
 }
 
+template <typename T, int MODE, int NS>
+void launch_kc_batch_n(lise_batch* b, const BatchGroup& g, int st, const cpx<T>* twN, hipStream_t s) {
+    if constexpr (cube_side((int)sizeof(T), NS)) {
+        const char* base = static_cast<const char*>(b->dtab);
+        const auto* tab = reinterpret_cast<const KPArgs<T>*>(base + g.off_kp[st][MODE == KP_ABM1 ? 0 : 1]);
+        const auto* rows = reinterpret_cast<const int*>(base + g.off_rows);
+        hipLaunchKernelGGL((kc_fast_batch<T, NS, MODE>), dim3(1, (unsigned)g.rows),
+                           dim3(cube_threads_of((int)sizeof(T), NS)), cube_lds_of((int)sizeof(T), NS), s, tab, rows,
+                           (int)g.sys.size(), twN);
+    }
+}
+
 template <typename T, int MODE>
 int launch_kp_batch(lise_batch* b, const BatchGroup& g, int st, hipStream_t s) {
     const lise_ctx* c0 = b->sys[g.sys[0]];
     const cpx<T>* twN = reinterpret_cast<const cpx<T>*>(c0->tw) + c0->tw_full_xy;
     hipEvent_t ev;
     bprof_begin(b, &ev, s);
+    if (g.cube) {
+        switch (g.nx) {
+            case 8: launch_kc_batch_n<T, MODE, 8>(b, g, st, twN, s); break;
+            case 16: launch_kc_batch_n<T, MODE, 16>(b, g, st, twN, s); break;
+            default: launch_kc_batch_n<T, MODE, 20>(b, g, st, twN, s); break;
+        }
+        bprof_end(b, MODE == KP_ABM1 ? 0 : 3, ev, s);
+        return bcheck_launch(b, "kc_fast_batch");
+    }
     switch (g.nx) {
         case 8: launch_kp_batch_n<T, MODE, 8>(b, g, st, twN, s); break;
         case 16: launch_kp_batch_n<T, MODE, 16>(b, g, st, twN, s); break;
@@ -1706,17 +1819,27 @@ int launch_kp_batch(lise_batch* b, const BatchGroup& g, int st, hipStream_t s) {
     return bcheck_launch(b, "kp_fast_batch");
 }
 
+template <typename T, int NZ, int L>
+void launch_kz_batch_l(lise_batch* b, const BatchGroup& g, int st, int ph, bool nt, hipStream_t s) {
+    if constexpr (kz_lanes_valid(NZ, L)) {
+        const char* base = static_cast<const char*>(b->dtab);
+        const auto* tab = reinterpret_cast<const KZFastArgs<T>*>(base + g.off_kz[st][ph]);
+        const auto* blks = reinterpret_cast<const long long*>(base + g.off_blks);
+        const dim3 grid((unsigned)g.zblocks);
+        if (nt)
+            hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, true>), grid, dim3(kThreads), 0, s, tab, blks,
+                               (int)g.sys.size());
+        else
+            hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, false>), grid, dim3(kThreads), 0, s, tab, blks,
+                               (int)g.sys.size());
+    }
+}
+
 template <typename T, int NZ>
 void launch_kz_batch_n(lise_batch* b, const BatchGroup& g, int st, int ph, bool nt, hipStream_t s) {
-    constexpr int L = kz_lanes<NZ>();
-    const char* base = static_cast<const char*>(b->dtab);
-    const auto* tab = reinterpret_cast<const KZFastArgs<T>*>(base + g.off_kz[st][ph]);
-    const auto* blks = reinterpret_cast<const long long*>(base + g.off_blks);
-    const dim3 grid((unsigned)g.zblocks);
-    if (nt)
-        hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, true>), grid, dim3(kThreads), 0, s, tab, blks, (int)g.sys.size());
-    else
-        hipLaunchKernelGGL((kz_fast_batch<T, NZ, L, false>), grid, dim3(kThreads), 0, s, tab, blks, (int)g.sys.size());
+    if (g.zl == 4) launch_kz_batch_l<T, NZ, 4>(b, g, st, ph, nt, s);
+    else if (g.zl == 2) launch_kz_batch_l<T, NZ, 2>(b, g, st, ph, nt, s);
+    else launch_kz_batch_l<T, NZ, 1>(b, g, st, ph, nt, s);
 }
 
 template <typename T>
@@ -1739,7 +1862,7 @@ int launch_kz_batch(lise_batch* b, const BatchGroup& g, int st, int ph, hipStrea
 
 template <typename T>
 int batch_phase_group(lise_batch* b, const BatchGroup& g, int st, int ph, hipStream_t s) {
-    BCHK(launch_kz_batch<T>(b, g, st, ph, s));
+    if (!g.cube) BCHK(launch_kz_batch<T>(b, g, st, ph, s));
     return ph == 0 ? launch_kp_batch<T, KP_ABM1>(b, g, st, s) : launch_kp_batch<T, KP_ABM2>(b, g, st, s);
 }
 
@@ -2184,10 +2307,14 @@ int lise_set_stream(lise_ctx* c, void* hip_stream) {
 int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     if (!c || !t) return LISE_E_ARG;
     if (t->chunk_qpwf < 0 || t->jgroup < 0) return fail(c, LISE_E_ARG, "negative tuning value");
+    if (t->z_lanes != 0 && t->z_lanes != 1 && t->z_lanes != 2 && t->z_lanes != 4)
+        return fail(c, LISE_E_ARG, "z_lanes must be 0, 1, 2 or 4");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->s2) HIPCHK(c, hipStreamSynchronize(c->s2));
     c->chunk = t->chunk_qpwf;
-    if (t->jgroup > 0) c->jg = t->jgroup;
+    c->jg_user = t->jgroup;
+    c->single_pass = t->single_pass < 0 ? -1 : (t->single_pass > 0 ? 1 : 0);
+    c->zl_user = t->z_lanes;
     c->fused_mode = t->fused < 0 ? -1 : (t->fused > 0 ? 1 : 0);
     c->generic = t->generic ? 1 : 0;
     c->overlap = t->no_overlap ? 0 : 1;
@@ -2521,6 +2648,26 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
     // steps, so that timing noise between close candidates does not decide
     std::vector<std::pair<float, lise_tuning>> timed;
     int rc = LISE_OK;
+    // the single-pass kernel where it applies (its chunk only splits launches;
+    // no z kernel to overlap), then the two-kernel path
+    const bool cube_ok = c->single_pass >= 0 && cube_eligible(c);   // both paths are candidates
+    if (cube_ok) {
+        const int cjgs[] = {2, 4, 8, 16};
+        for (int jg : cjgs) {
+            if (rc != LISE_OK) break;
+            lise_tuning t{};
+            t.chunk_qpwf = (int32_t)std::min<long long>(c->M, gib);
+            t.jgroup = jg;
+            t.fused = c->fused_mode;
+            t.generic = c->generic;
+            t.no_overlap = 1;
+            t.graph = c->use_graph;
+            t.single_pass = 1;
+            float ms = 0.0f;
+            rc = trial(t, trial_steps, &ms);
+            if (rc == LISE_OK) timed.push_back({ms, t});
+        }
+    }
     for (long long ch : chunks)
         for (int jg : jgs)
             for (int nov = 0; nov < 2 && rc == LISE_OK; ++nov) {
@@ -2532,6 +2679,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
                 t.generic = c->generic;
                 t.no_overlap = nov;
                 t.graph = c->use_graph;
+                t.single_pass = cube_ok ? -1 : c->single_pass;
                 float ms = 0.0f;
                 rc = trial(t, trial_steps, &ms);
                 if (rc == LISE_OK) timed.push_back({ms, t});
@@ -2541,12 +2689,25 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
         std::sort(timed.begin(), timed.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
         best = timed[0].second;
         float best_ms = 1e30f;
-        for (size_t i = 0; i < std::min<size_t>(3, timed.size()) && rc == LISE_OK; ++i) {
+        // second round: the three fastest, each also with 2 and 4 lanes per
+        // z-column where the z kernel runs (two-kernel path, lanes valid)
+        std::vector<lise_tuning> second;
+        for (size_t i = 0; i < std::min<size_t>(3, timed.size()); ++i) {
+            lise_tuning t = timed[i].second;
+            second.push_back(t);
+            if (t.single_pass > 0 || !c->fast_z) continue;
+            for (int zl : {2, 4})
+                if (kz_lanes_valid(c->lat.nz, zl)) {
+                    t.z_lanes = zl;
+                    second.push_back(t);
+                }
+        }
+        for (size_t i = 0; i < second.size() && rc == LISE_OK; ++i) {
             float ms = 0.0f;
-            rc = trial(timed[i].second, 2 * trial_steps, &ms);
+            rc = trial(second[i], 2 * trial_steps, &ms);
             if (rc == LISE_OK && ms < best_ms) {
                 best_ms = ms;
-                best = timed[i].second;
+                best = second[i];
             }
         }
     }

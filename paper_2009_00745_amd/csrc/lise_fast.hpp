@@ -310,8 +310,14 @@ __global__ void __launch_bounds__(256) kz_fast(const KZFastArgs<T> a) {
 #define LISE_KZ_LANES 1
 #endif
 
+// a column of nz points over L lanes: L divides nz and each lane keeps >= 2 points
+__host__ __device__ constexpr bool kz_lanes_valid(int nz, int L) {
+    return L == 1 || (nz % L == 0 && nz / L >= 2);
+}
+
+// default lanes per column
 __host__ __device__ constexpr int kz_lanes_of(int nz) {
-    return (LISE_KZ_LANES > 1 && nz % LISE_KZ_LANES == 0 && nz / LISE_KZ_LANES >= 2) ? LISE_KZ_LANES : 1;
+    return (LISE_KZ_LANES > 1 && kz_lanes_valid(nz, LISE_KZ_LANES)) ? LISE_KZ_LANES : 1;
 }
 
 template <int NZ>

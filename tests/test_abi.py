@@ -83,3 +83,27 @@ def test_library_coupling_rejects_bad_input():
         assert abs(v) > 1e12
     except lise.LiseError:
         pass
+
+
+def _header_struct_fields(name):
+    import re
+    text = open(os.path.join(ROOT, "include", "lise.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} " + name + ";", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1]
+        fields += [n.strip().split("[")[0] for n in names.split(",")]
+    return fields
+
+
+def test_binding_structs_match_header():
+    """The ctypes structures carry the header's fields in the header's order."""
+    from paper_2009_00745_amd import lise as binding
+    pairs = [("lise_tuning", binding.Tuning), ("lise_lattice", binding.Lattice),
+             ("lise_functional", binding.Functional), ("lise_obs", binding.Obs)]
+    for cname, py in pairs:
+        assert _header_struct_fields(cname) == [f for f, _ in py._fields_], cname

@@ -188,3 +188,34 @@ def test_batch_errors(lise):
         lise.Batch([c1, c1])
     c1.close()
     c2.close()
+
+
+def test_batch_single_pass_groups_match_individual(lise):
+    """Systems on the single-pass kernel (16^3 FP64, 20^3 FP32, 8^3 C = 4) grouped with the
+    batched single-pass launch, graph replays on, 9 steps: each equals itself alone with the
+    same tuning, bit for bit."""
+    ws = [wl.config2(M=12, n=16), wl.config2(M=7, n=16, seed=2), wl.config3(M=10, n=20, precision=wl.FP32),
+          wl.config4(M=6, n=8, precision=wl.FP64)]
+    dt = 0.002
+    say("batch, single-pass groups: 4 systems, 9 steps")
+    ctxs = []
+    for w in ws:
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_tuning(single_pass=1)
+        c.set_qpwf(0, w.qpwfs())
+        ctxs.append(c)
+    b = lise.Batch(ctxs)
+    b.step(dt, 9)
+    assert b.info() == (3, 0)
+    got = [c.get_qpwf(0, w.M) for c, w in zip(ctxs, ws)]
+    b.close()
+    for c in ctxs:
+        c.close()
+    for w, g in zip(ws, got):
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_tuning(single_pass=1)
+        c.set_qpwf(0, w.qpwfs())
+        c.step(dt, 9)
+        ref = c.get_qpwf(0, w.M)
+        c.close()
+        assert np.array_equal(g, ref), w.name

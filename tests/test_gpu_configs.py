@@ -161,3 +161,36 @@ def test_set_qpwf_requires_every_qpwf(lise):
     ev.step(w.dt, 1)
     assert rel_l2(ctx.get_qpwf(0, w.M), ev.y) < 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("zl", [2, 4])
+def test_z_lanes_steps_match_oracle(lise, zl):
+    """The z-axis kernel with 2 or 4 lanes per column (the autotuner's z_lanes choice):
+    32^3 FP64 and 24^3 FP32 steps against the oracle (1e-11, 1e-5), and a batch of both
+    equal to the systems alone bit for bit."""
+    cases = [(wl.config2(M=5, n=32), 1e-11), (wl.config3(M=6, n=24, precision=wl.FP32), 1e-5)]
+    outs = []
+    for w, tol in cases:
+        say(f"z lanes {zl}: {w.name} 8 steps")
+        g = gpu_run(lise, w, 8, tuning={"z_lanes": zl})
+        w64 = wl.config2(M=5, n=32) if w.functional.precision == wl.FP64 else wl.config3(M=6, n=24, precision=wl.FP64)
+        ev = oracle_run(w64, 8)
+        n0, k0 = oracle.densities(ev.y, w64.functional)
+        e = (rel_l2(g["dens"][0], n0), rel_l2(g["dens"][1], k0))
+        say(f"  density rel L2 n {e[0]:.3e} kappa {e[1]:.3e}")
+        assert max(e) < tol
+        outs.append(g["psi"])
+    ctxs = []
+    for w, _ in cases:
+        c = lise.Context(w.lattice, w.M, w.functional)
+        c.set_tuning(z_lanes=zl)
+        c.set_qpwf(0, w.qpwfs())
+        ctxs.append(c)
+    b = lise.Batch(ctxs)
+    b.step(cases[0][0].dt, 8)
+    got = [c.get_qpwf(0, w.M) for c, (w, _) in zip(ctxs, cases)]
+    b.close()
+    for c in ctxs:
+        c.close()
+    for g, ref in zip(got, outs):
+        assert np.array_equal(g, ref)
