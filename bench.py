@@ -435,6 +435,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--jgroup", type=int, default=0)
     ap.add_argument("--no-overlap", action="store_true", help="z kernel on the same stream as the plane kernel")
+    ap.add_argument("--z-lanes", type=int, default=0, help="lanes per z-column of the z kernel (1, 2, 4; 0 = default)")
+    ap.add_argument("--single-pass", type=int, default=0,
+                    help="1 = the single-pass ABM kernel wherever it fits, -1 = never, 0 = library default")
     ap.add_argument("--graph", action="store_true", help="replay four-step HIP graphs (kept by the autotuner)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -485,10 +488,10 @@ def main():
 
     w = make_workload(args.workload, M=args.M)
     tuning = {}
-    fixed_shape = bool(args.chunk or args.jgroup or args.no_overlap)
+    fixed_shape = bool(args.chunk or args.jgroup or args.no_overlap or args.z_lanes or args.single_pass)
     if fixed_shape or args.graph:
         tuning = {"chunk_qpwf": args.chunk, "jgroup": args.jgroup, "no_overlap": int(args.no_overlap),
-                  "graph": int(args.graph)}
+                  "graph": int(args.graph), "z_lanes": args.z_lanes, "single_pass": args.single_pass}
     C, N = w.functional.ncomp, w.lattice.n
     esz = 16 if w.functional.precision == 0 else 8
     autotune = not args.no_autotune and not fixed_shape
