@@ -172,12 +172,15 @@ typedef struct {
  *                that holds the whole component pair of a qpwf in LDS and
  *                applies the kinetic term as a 3D transform, instead of the
  *                z-axis kernel plus the plane kernel (no z-term scratch: 14
- *                state arrays per step instead of 20).  1 = wherever
- *                available, 0 = default (side 8 only: there it measured
- *                faster, at 16 and 20 slower), -1 = never; start-up,
- *                lise_apply_h and the observables keep the two kernels.
- *                jgroup's default is 4 qpwfs per workgroup on this path (32
- *                on the others).  lise_autotune times both paths.
+ *                state arrays per step instead of 20; at side 20 and in
+ *                float64 at side 16 the densities take a pass of their
+ *                own, 16 arrays).  1 = wherever available, 0 = default
+ *                (side 8, and 16 and 20 in LISE_FP32: measured faster there
+ *                than the two kernels; float64 at 16 slower), -1 = never;
+ *                start-up, lise_apply_h and the observables keep the two
+ *                kernels.  jgroup's default is 16 qpwfs per workgroup on
+ *                this path (32 on the others).  lise_autotune times both
+ *                paths.
  *   z_lanes    : lanes that share one z-column in the register-FFT z-axis
  *                kernel: 1 (the column in one thread's registers), 2 or 4
  *                (each lane nz/L points, exchanges across lanes); 0 =

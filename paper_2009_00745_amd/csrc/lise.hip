@@ -33,7 +33,8 @@ constexpr int kThreads = 256;
 const char* kVersion = "lise-mi355x 0.1 (gfx950)";
 constexpr int kBatchPeriod = 4;   // ABM steps after which the buffer ring repeats
 constexpr int kPlaneJg = 32;      // default qpwfs per workgroup row of the plane kernels
-constexpr int kCubeJg = 4;        // ... of the single-pass kernel (one workgroup holds a whole qpwf)
+constexpr int kCubeJg = 16;       // ... of the single-pass kernel (one workgroup holds a whole qpwf)
+constexpr size_t kDescRowsOffset = 1024;   // the one-entry table of a single system: descriptor, then rows
 
 // Staging memory of lise_apply_h_noalloc: one fixed array per GPU, held until
 // the process ends, shared by every context on that GPU.  Host code never
@@ -94,6 +95,7 @@ struct lise_ctx {
     void* ah_buf = nullptr;    // staging of lise_apply_h (one piece, kept)
     size_t ah_cap = 0;
     void* scratch_dev = nullptr;  // this device's address of `scratch` (lise_apply_h_noalloc)
+    void* cube_desc = nullptr;    // one-entry descriptor table of the single-pass kernel
     double* red = nullptr;     // reduction partials (observables)
     long long red_cap = 0;
     double* pz_part = nullptr;  // per-workgroup z-momentum sums (observables)
@@ -259,8 +261,6 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if constexpr (cube_side((int)sizeof(T), NS)) {
-        (void)hipFuncSetAttribute((const void*)kc_fast<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void*)kc_fast<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     }
@@ -347,10 +347,12 @@ int configure(lise_ctx* c) {
     if (c->fast_xy || c->mfma_xy) c->zb = 1;
     c->zl = (c->zl_user > 0 && kz_lanes_valid(nz, c->zl_user)) ? c->zl_user : kz_lanes_of(nz);
     // single-pass ABM kernel: the whole pair of component cubes in LDS; by
-    // default only on 8^3 (measured 2.4x faster there, 2x slower than the
-    // two kernels at 16^3 and 20^3)
-    c->cube = cube_eligible(c) && (c->single_pass > 0 || (c->single_pass == 0 && nx == 8));
+    // default where it measured faster than the two kernels
+    c->cube = cube_eligible(c) &&
+              (c->single_pass > 0 || (c->single_pass == 0 && cube_auto_of((int)c->esz / 2, nx)));
     c->jg = c->jg_user > 0 ? c->jg_user : (c->cube ? kCubeJg : kPlaneJg);
+    static_assert(sizeof(KPArgs<double>) <= kDescRowsOffset, "descriptor table layout");
+    if (c->cube && !c->cube_desc) CHK(dalloc(c, &c->cube_desc, kDescRowsOffset + 64));
     c->stream_hint = c->mfma_xy || (c->fast_xy && plane_stream_hint_of(c->esz / 2, nx));
     // the generic LDS kernels must fit where they are the ones that run
     if (!c->fused && !c->fast_xy && !c->mfma_xy && kp_lds_bytes(c, c->zb) > c->lds_limit)
@@ -630,13 +632,18 @@ int launch_kz_t(lise_ctx* c, const cpx<T>* in, long long j0, int k, void* Gdst, 
     return check_launch(c, "kz_kernel");
 }
 
+int slots_used(const lise_ctx* c, long long count);
+
 // The single-pass ABM kernel (lise_cube.hpp): the kinetic factors carry
 // 1 / N^3 of the 3D round trip.
 template <typename T, int N, int MODE>
 void launch_kc_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
     if constexpr (cube_side((int)sizeof(T), N)) {
-        hipLaunchKernelGGL((kc_fast<T, N, MODE>), grid, dim3(cube_threads_of((int)sizeof(T), N)),
-                           cube_lds_of((int)sizeof(T), N), c->stream, a,
+        auto* desc = reinterpret_cast<KPArgs<T>*>(c->cube_desc);
+        int* rows = reinterpret_cast<int*>(static_cast<char*>(c->cube_desc) + kDescRowsOffset);
+        hipLaunchKernelGGL((put_desc_kernel<T>), dim3(1), dim3(64), 0, c->stream, a, (int)grid.y, desc, rows);
+        hipLaunchKernelGGL((kc_fast_batch<T, N, MODE>), grid, dim3(cube_threads_of((int)sizeof(T), N)),
+                           cube_lds_of((int)sizeof(T), N), c->stream, desc, rows, 1,
                            reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
     }
 }
@@ -656,6 +663,9 @@ int launch_kc_t(lise_ctx* c, KPArgs<T> a, long long j0, int k, int cls) {
     a.j0 = j0;
     a.kcount = k;
     cube_factors<T>(c, a);
+    // the kernel reads its descriptor from this device table (written first
+    // on the stream); it lives from configure to lise_free
+    if (!c->cube_desc) return fail(c, LISE_E_STATE, "single-pass descriptor table is not allocated");
     dim3 grid(1, (unsigned)((k + a.jg - 1) / a.jg));
     hipEvent_t ev;
     prof_begin(c, cls, &ev);
@@ -723,6 +733,20 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
                 a.G = nullptr;
                 a.accumulate = (dens && ci > 0) ? 1 : 0;
                 CHK((launch_kc_t<T, MODE>(c, a, j0, k, cls)));
+            }
+            if (dens && !cube_dens_in_of((int)c->esz / 2, c->lat.nx)) {
+                // densities of the vector the phase wrote (m or y_{n+1}) in a
+                // pass of their own, into as many slots as the fields kernel sums
+                const cpx<T>* v = MODE == KP_ABM1 ? a.a4 : a.a1;
+                const long long slots = slots_used(c, c->M);
+                const int jgd = (int)((c->M + slots - 1) / slots);
+                dim3 grid((unsigned)((c->N + kThreads - 1) / kThreads), (unsigned)slots);
+                hipEvent_t ev;
+                prof_begin(c, 2, &ev);
+                hipLaunchKernelGGL((dens_partial_kernel<T>), grid, dim3(kThreads), 0, c->stream, v, c->C, c->N, c->M,
+                                   jgd, c->C == 2 ? c->fn.w : 1.0, c->dpart);
+                prof_end(c, 2, ev);
+                CHK(check_launch(c, "dens_partial_kernel"));
             }
             return LISE_OK;
         }
@@ -1452,7 +1476,11 @@ struct BatchGroup {
     int prec = LISE_FP64;
     int nx = 0, nz = 0;
     bool cube = false;             // single-pass kernel, no z-axis launch or z-scratch
+    bool dens_split = false;       // single-pass kernel without densities: a density pass follows
     int zl = 1;                    // lanes per z-column
+    long long dblocks = 0;         // workgroups of the density pass
+    size_t off_dblks = 0;
+    size_t off_dens[kBatchPeriod][2] = {};
     std::vector<int> sys;          // indices into lise_batch::sys
     std::vector<size_t> goff;      // byte offset of each system's region of the z-scratch
     size_t gbytes = 0;             // z-scratch of the group: sum of M * C * N elements
@@ -1535,6 +1563,10 @@ bool batch_groupable(const lise_ctx* c) {
     return c->fast_xy && c->fast_z && !c->mfma_xy && !c->fused && !c->remove_phase && !c->generic;
 }
 
+// slots and slot width of the separate density pass (as apply_chunks)
+long long split_slots(const lise_ctx* c) { return slots_used(c, c->M); }
+int split_jgd(const lise_ctx* c) { return (int)((c->M + split_slots(c) - 1) / split_slots(c)); }
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Ring state of system c after `step` steps from the tables' base state.
@@ -1556,6 +1588,12 @@ void batch_fill_group(lise_batch* b, const BatchGroup& g, std::vector<unsigned c
     }
     std::memcpy(h.data() + g.off_rows, rows.data(), rows.size() * sizeof(int));
     std::memcpy(h.data() + g.off_blks, blks.data(), blks.size() * sizeof(long long));
+    std::vector<long long> dblks(ns + 1, 0);
+    for (int i = 0; i < ns; ++i) {
+        const lise_ctx* c = b->sys[g.sys[i]];
+        dblks[i + 1] = dblks[i] + split_slots(c) * ((c->N + kThreads - 1) / kThreads);
+    }
+    std::memcpy(h.data() + g.off_dblks, dblks.data(), dblks.size() * sizeof(long long));
     for (int st = 0; st < kBatchPeriod; ++st)
         for (int ph = 0; ph < 2; ++ph)
             for (int i = 0; i < ns; ++i) {
@@ -1607,6 +1645,17 @@ void batch_fill_group(lise_batch* b, const BatchGroup& g, std::vector<unsigned c
                 f.ezpart = nullptr;
                 f.nu = c->C == 2 ? 1 : 2;
                 std::memcpy(h.data() + g.off_kz[st][ph] + i * sizeof(KZFastArgs<T>), &f, sizeof(f));
+                DensDesc<T> dd;
+                std::memset(&dd, 0, sizeof(dd));
+                dd.v = ph == 0 ? a.a4 : a.a1;   // m, or y_{n+1}
+                dd.N = c->N;
+                dd.M = c->M;
+                dd.C = c->C;
+                dd.jgd = split_jgd(c);
+                dd.w = c->C == 2 ? c->fn.w : 1.0;
+                dd.dpart = c->dpart;
+                dd.bx = (c->N + kThreads - 1) / kThreads;
+                std::memcpy(h.data() + g.off_dens[st][ph] + i * sizeof(DensDesc<T>), &dd, sizeof(dd));
             }
 }
 
@@ -1639,6 +1688,7 @@ int batch_build(lise_batch* b, double dt) {
             g->nx = c->lat.nx;
             g->nz = c->lat.nz;
             g->cube = c->cube;
+            g->dens_split = c->cube && !cube_dens_in_of((int)c->esz / 2, c->lat.nx);
             g->zl = c->zl;
         }
         g->sys.push_back(i);
@@ -1647,6 +1697,7 @@ int batch_build(lise_batch* b, double dt) {
         g->qpwfs += c->M;
         g->rows += (int)((c->M + c->jg - 1) / c->jg);
         g->zblocks += (c->M * c->C * (long long)c->lat.nx * c->lat.ny * c->zl + kThreads - 1) / kThreads;
+        g->dblocks += split_slots(c) * ((c->N + kThreads - 1) / kThreads);
         b->grouped.push_back(i);
     }
     if (b->grouped.empty()) return LISE_OK;
@@ -1680,12 +1731,17 @@ int batch_build(lise_batch* b, double dt) {
         off = align256(off + (n + 1) * sizeof(int));
         g.off_blks = off;
         off = align256(off + (n + 1) * sizeof(long long));
+        g.off_dblks = off;
+        off = align256(off + (n + 1) * sizeof(long long));
+        const size_t dd_sz = g.prec == LISE_FP64 ? sizeof(DensDesc<double>) : sizeof(DensDesc<float>);
         for (int st = 0; st < kBatchPeriod; ++st)
             for (int ph = 0; ph < 2; ++ph) {
                 g.off_kp[st][ph] = off;
                 off = align256(off + n * kp_sz);
                 g.off_kz[st][ph] = off;
                 off = align256(off + n * kz_sz);
+                g.off_dens[st][ph] = off;
+                off = align256(off + n * dd_sz);
             }
     }
     const size_t ng = b->grouped.size();
@@ -1729,7 +1785,10 @@ int batch_build(lise_batch* b, double dt) {
             FieldsDesc d;
             std::memset(&d, 0, sizeof(d));
             d.dpart = c->dpart;
-            d.nslots = (int)((c->M + c->jg - 1) / c->jg);
+            // the slots the plane or single-pass kernel writes (one per workgroup
+            // row), or those of the separate density pass
+            d.nslots = (c->cube && !cube_dens_in_of((int)c->esz / 2, c->lat.nx)) ? (int)split_slots(c)
+                                                                               : (int)((c->M + c->jg - 1) / c->jg);
             d.N = c->N;
             d.dens = ph == 0 ? c->dens_tmp : c->dens_cur;
             d.V = ph == 0 ? c->V_tmp : c->V_cur;
@@ -1863,7 +1922,17 @@ int launch_kz_batch(lise_batch* b, const BatchGroup& g, int st, int ph, hipStrea
 template <typename T>
 int batch_phase_group(lise_batch* b, const BatchGroup& g, int st, int ph, hipStream_t s) {
     if (!g.cube) BCHK(launch_kz_batch<T>(b, g, st, ph, s));
-    return ph == 0 ? launch_kp_batch<T, KP_ABM1>(b, g, st, s) : launch_kp_batch<T, KP_ABM2>(b, g, st, s);
+    const int rc = ph == 0 ? launch_kp_batch<T, KP_ABM1>(b, g, st, s) : launch_kp_batch<T, KP_ABM2>(b, g, st, s);
+    if (rc != LISE_OK) return rc;
+    if (!g.dens_split) return LISE_OK;
+    const char* base = static_cast<const char*>(b->dtab);
+    hipEvent_t ev;
+    bprof_begin(b, &ev, s);
+    hipLaunchKernelGGL((dens_batch_kernel<T>), dim3((unsigned)g.dblocks), dim3(kThreads), 0, s,
+                       reinterpret_cast<const DensDesc<T>*>(base + g.off_dens[st][ph]),
+                       reinterpret_cast<const long long*>(base + g.off_dblks), (int)g.sys.size());
+    bprof_end(b, 2, ev, s);
+    return bcheck_launch(b, "dens_batch_kernel");
 }
 
 // One ABM step of every grouped system (the enqueue only): per phase, the
@@ -2785,6 +2854,7 @@ void lise_free(lise_ctx* c) {
     dfree(&c->tw);
     dfree(reinterpret_cast<void**>(&c->red));
     dfree(&c->ah_buf);
+    dfree(&c->cube_desc);
     dfree(reinterpret_cast<void**>(&c->norms));
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->eta));

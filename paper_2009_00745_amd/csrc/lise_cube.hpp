@@ -36,6 +36,15 @@ __host__ __device__ constexpr bool cube_keep_of(int esz, int N) { return N <= 8;
 
 __host__ __device__ constexpr bool cube_side(int esz, int N) { return N == 8 || N == 16 || (N == 20 && esz == 4); }
 
+// where the single-pass kernel is the default (measured faster than the two
+// kernels: side 8 in both precisions, 16 and 20 in float32)
+__host__ __device__ constexpr bool cube_auto_of(int esz, int N) { return N == 8 || (esz == 4 && (N == 16 || N == 20)); }
+
+// float64 density accumulators of the epilogue points in registers (else the
+// kernel leaves the densities to a separate pass over the vector it wrote:
+// one more array read per phase, and registers for the transforms instead)
+__host__ __device__ constexpr bool cube_dens_in_of(int esz, int N) { return N == 8 || (N == 16 && esz == 4); }
+
 // dynamic LDS of the kernel: twiddles + two padded cubes
 __host__ __device__ constexpr size_t cube_lds_of(int esz, int N) {
     return (size_t)(N + 2 * cube_comp(N)) * 2 * esz;
@@ -86,26 +95,33 @@ __device__ __forceinline__ void cube_line(cpx<T>* __restrict__ L, const cpx<T>* 
 
 // One workgroup row `by` of qpwfs (jg of them); MODE is KP_ABM1 or KP_ABM2.
 // a.cx, a.cy, a.cz carry (2 pi^2 / L_a^2) / N^3.
+// ap is __restrict__: the kernel's stores through the state pointers never
+// modify the descriptor, so its fields stay in scalar registers (the batched
+// kernel reads it from a device table)
 template <typename T, int N, int MODE>
-__device__ __forceinline__ void kc_fast_body(const KPArgs<T>& a, const cpx<T>* __restrict__ twN, const int by) {
+__device__ __forceinline__ void kc_fast_body(const KPArgs<T>* __restrict__ ap, const cpx<T>* __restrict__ twN,
+                                             const int by) {
+    const KPArgs<T>& a = *ap;
     static_assert(MODE == KP_ABM1 || MODE == KP_ABM2, "single-pass kernel of the ABM phases");
     constexpr int NTH = cube_threads_of((int)sizeof(T), N);
     constexpr bool KEEP = cube_keep_of((int)sizeof(T), N);
     constexpr int NN = N * N, N3 = N * N * N, RW = cube_row(N), PL = N * RW, CS = cube_comp(N);
     constexpr int PN = (N3 + NTH - 1) / NTH;
     constexpr int KN = KEEP ? PN : 1;
+    constexpr bool DIN = cube_dens_in_of((int)sizeof(T), N);
+    constexpr int DN = DIN ? PN : 1;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* L = tab + N;
     const int tid = threadIdx.x;
-    for (int i = tid; i < N; i += NTH) tab[i] = twN[i];
+    for (int i = tid; i < N; i += NTH) tab[i] = ld_hint<T, false>(twN + i);
     const int jbeg = by * a.jg;
     const int jend = min(a.kcount, jbeg + a.jg);
     const T cdt = T(a.dt / 48.0);
     const cpx<T> coef = mk(T(0), T(0));
-    double dn[PN], dkr[PN], dki[PN];
+    double dn[DN], dkr[DN], dki[DN];
 #pragma unroll
-    for (int q = 0; q < PN; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
+    for (int q = 0; q < DN; ++q) dn[q] = dkr[q] = dki[q] = 0.0;
     double ekin = 0.0;
     __syncthreads();
     for (int jl = jbeg; jl < jend; ++jl) {
@@ -117,7 +133,10 @@ __device__ __forceinline__ void kc_fast_body(const KPArgs<T>& a, const cpx<T>* _
             cpx<T> fa[KN], fb[KN];
 #pragma unroll
             for (int i = 0; i < PN; ++i) {
-                const int p = tid + i * NTH;
+                int p = tid + i * NTH;
+                // recomputed per qpwf rather than hoisted out of the qpwf loop
+                // (the hoisted per-point offsets did not fit in registers)
+                asm volatile("" : "+v"(p));
                 if (p < N3) {
                     // read once when kept; read again later otherwise (no
                     // nontemporal hint then, so that the second read can hit)
@@ -138,12 +157,15 @@ __device__ __forceinline__ void kc_fast_body(const KPArgs<T>& a, const cpx<T>* _
 #pragma unroll 1
             for (int pass = 0; pass < 5; ++pass) {
                 const int axis = pass < 3 ? pass : 4 - pass;
-                if (act) cube_line<T, N>(L, tab, tid, axis, pass > 2, a);
+                int t = tid;
+                asm volatile("" : "+v"(t));
+                if (act) cube_line<T, N>(L, tab, t, axis, pass > 2, a);
                 __syncthreads();
             }
 #pragma unroll
             for (int i = 0; i < PN; ++i) {
-                const int p = tid + i * NTH;
+                int p = tid + i * NTH;
+                asm volatile("" : "+v"(p));
                 if (p < N3) {
                     const int l = (p / NN) * PL + ((p / N) % N) * RW + p % N;
                     cpx<T> u, v;
@@ -155,7 +177,8 @@ __device__ __forceinline__ void kc_fast_body(const KPArgs<T>& a, const cpx<T>* _
                         v = ld_hint<T, false>(a.in + offb + p);
                     }
                     point_epilogue<T, MODE, false, true>(a, pr, L[l], L[CS + l], u, v, offa + p, offb + p, p, 0, 0,
-                                                         coef, cdt, ej, dn[i], dkr[i], dki[i], ekin);
+                                                         coef, cdt, ej, dn[DIN ? i : 0], dkr[DIN ? i : 0],
+                                                         dki[DIN ? i : 0], ekin);
                 }
                 // one point's loads in flight at a time per thread: the
                 // workgroup's 16 waves keep enough requests in flight, and
@@ -165,38 +188,44 @@ __device__ __forceinline__ void kc_fast_body(const KPArgs<T>& a, const cpx<T>* _
             __syncthreads();   // the cubes are rewritten by the next pair
         }
     }
-    if (a.dens_src) {
+    if (DIN && a.dens_src) {
         double* base = a.dpart + (long long)by * 3 * N3;
 #pragma unroll
         for (int i = 0; i < PN; ++i) {
             const int p = tid + i * NTH;
             if (p >= N3) continue;
             if (a.accumulate) {
-                base[p] += dn[i];
-                base[N3 + p] += dkr[i];
-                base[2 * N3 + p] += dki[i];
+                stg(base + p, ldg(base + p) + dn[i]);
+                stg(base + N3 + p, ldg(base + N3 + p) + dkr[i]);
+                stg(base + 2 * N3 + p, ldg(base + 2 * N3 + p) + dki[i]);
             } else {
-                base[p] = dn[i];
-                base[N3 + p] = dkr[i];
-                base[2 * N3 + p] = dki[i];
+                stg(base + p, dn[i]);
+                stg(base + N3 + p, dkr[i]);
+                stg(base + 2 * N3 + p, dki[i]);
             }
         }
     }
 }
 
-template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((cube_threads_of((int)sizeof(T), N))) kc_fast(const KPArgs<T> a,
-                                                                               const cpx<T>* __restrict__ twN) {
-    kc_fast_body<T, N, MODE>(a, twN, (int)blockIdx.y);
-}
-
-// Systems of one lattice side in one launch (see kp_fast_batch).
+// Systems of one lattice side in one launch (see kp_fast_batch).  A single
+// system runs the same kernel on a one-entry table (put_desc_kernel writes
+// it on the stream), so that a system stepped alone and in a batch execute
+// identical code and round identically.
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((cube_threads_of((int)sizeof(T), N)))
     kc_fast_batch(const KPArgs<T>* __restrict__ tab, const int* __restrict__ rows, int nsys,
                   const cpx<T>* __restrict__ twN) {
     const int s = batch_find(rows, nsys, (int)blockIdx.y);
-    kc_fast_body<T, N, MODE>(tab[s], twN, (int)blockIdx.y - rows[s]);
+    kc_fast_body<T, N, MODE>(tab + s, twN, (int)blockIdx.y - rows[s]);
+}
+
+template <typename T>
+__global__ void put_desc_kernel(const KPArgs<T> a, int nrows, KPArgs<T>* __restrict__ dst, int* __restrict__ rows) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *dst = a;
+        rows[0] = 0;
+        rows[1] = nrows;
+    }
 }
 
 }  // namespace lise

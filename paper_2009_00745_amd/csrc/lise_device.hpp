@@ -71,27 +71,47 @@ template <>
 struct vec2_of<float> {
     typedef float type __attribute__((ext_vector_type(2)));
 };
+// The state arrays, fields and partial sums live in device global memory.
+// Pointers that a kernel reads from a descriptor table in memory (the batched
+// kernels) are generic to the compiler, which then emits flat instructions;
+// those also count against the LDS wait counter, so every wait for LDS data
+// would wait for outstanding memory traffic as well.  The accessors below
+// state the global address space explicitly (a no-op on the address).
+template <typename P>
+__device__ __forceinline__ const __attribute__((address_space(1))) P* gptr(const P* p) {
+    return (const __attribute__((address_space(1))) P*)p;
+}
+template <typename P>
+__device__ __forceinline__ __attribute__((address_space(1))) P* gptr(P* p) {
+    return (__attribute__((address_space(1))) P*)p;
+}
+template <typename P>
+__device__ __forceinline__ P ldg(const P* p) {
+    return *gptr(p);
+}
+template <typename P>
+__device__ __forceinline__ void stg(P* p, P v) {
+    *gptr(p) = v;
+}
+
 template <typename T, bool NT>
 __device__ __forceinline__ cpx<T> ld_hint(const cpx<T>* p) {
-    if constexpr (NT && LISE_STREAM_HINT) {
-        typedef typename vec2_of<T>::type V;
-        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-        return mk(T(v.x), T(v.y));
-    } else {
-        return *p;
-    }
+    typedef typename vec2_of<T>::type V;
+    const __attribute__((address_space(1))) V* q = reinterpret_cast<const __attribute__((address_space(1))) V*>(gptr(p));
+    V v;
+    if constexpr (NT && LISE_STREAM_HINT) v = __builtin_nontemporal_load(q);
+    else v = *q;
+    return mk(T(v.x), T(v.y));
 }
 template <typename T, bool NT>
 __device__ __forceinline__ void st_hint(cpx<T>* p, cpx<T> v) {
-    if constexpr (NT && LISE_STREAM_HINT) {
-        typedef typename vec2_of<T>::type V;
-        V w;
-        w.x = v.re;
-        w.y = v.im;
-        __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
-    } else {
-        *p = v;
-    }
+    typedef typename vec2_of<T>::type V;
+    __attribute__((address_space(1))) V* q = reinterpret_cast<__attribute__((address_space(1))) V*>(gptr(p));
+    V w;
+    w.x = v.re;
+    w.y = v.im;
+    if constexpr (NT && LISE_STREAM_HINT) __builtin_nontemporal_store(w, q);
+    else *q = w;
 }
 
 // multiply by i * sigma, sigma = +1 or -1
@@ -366,8 +386,8 @@ __device__ __forceinline__ void point_epilogue(const KPArgs<T>& a, int pr, cpx<T
         ekin += a.w * (double(fb.re) * double(Tb.re) + double(fb.im) * double(Tb.im));
         return;
     }
-    const double Vd = a.V[rpt];
-    const double Dre = a.D[2 * rpt], Dim = a.D[2 * rpt + 1];
+    const double Vd = ldg(a.V + rpt);
+    const double Dre = ldg(a.D + 2 * rpt), Dim = ldg(a.D + 2 * rpt + 1);
     cpx<T> h1a, h1b, h2a, h2b, h3a, h3b, h4a, h4b, h5a, h5b;
     if constexpr (MODE == KP_ABM1) {
         h1a = ld_hint<T, NT>(a.a1 + ea); h1b = ld_hint<T, NT>(a.a1 + eb);
@@ -880,6 +900,59 @@ __global__ void __launch_bounds__(256) dens_partial_kernel(const cpx<T>* __restr
     base[r] = n;
     base[N + r] = kr;
     base[2 * N + r] = ki;
+}
+
+// One system's part of a batched density pass (dens_partial_kernel on a
+// table): the vector v (M qpwfs of C components of N points), slots of jgd
+// qpwfs, weight w.
+template <typename T>
+struct DensDesc {
+    const cpx<T>* v;
+    long long N, M;
+    int C, jgd;
+    double w;
+    double* dpart;
+    long long bx;   // workgroups along the points: ceil(N / 256)
+};
+
+// Every system of a group in one launch: blks[s] is the first workgroup of
+// system s (blks[nsys] = gridDim.x); within a system, workgroup b takes the
+// points of block b % bx of slot b / bx.
+template <typename T>
+__global__ void __launch_bounds__(256) dens_batch_kernel(const DensDesc<T>* __restrict__ tab,
+                                                         const long long* __restrict__ blks, int nsys) {
+    int lo = 0, hi = nsys;
+    const long long b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blks[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const DensDesc<T>& d = tab[lo];
+    const long long lb = b - blks[lo];
+    const long long slot = lb / d.bx;
+    const long long r = (lb - slot * d.bx) * blockDim.x + threadIdx.x;
+    if (r >= d.N) return;
+    const long long j0 = slot * d.jgd;
+    const long long j1 = min(d.M, j0 + d.jgd);
+    double n = 0.0, kr = 0.0, ki = 0.0;
+    for (long long j = j0; j < j1; ++j) {
+        for (int pr = 0; pr < d.C / 2; ++pr) {
+            const int ca = (d.C == 2) ? 0 : pr;
+            const int cb = (d.C == 2) ? 1 : 3 - pr;
+            const double s = (pr == 0) ? 1.0 : -1.0;
+            const cpx<T> u = ld_hint<T, false>(d.v + (j * d.C + ca) * d.N + r);
+            const cpx<T> v = ld_hint<T, false>(d.v + (j * d.C + cb) * d.N + r);
+            const double br = double(v.re), bi = double(v.im), ar = double(u.re), ai = double(u.im);
+            n += d.w * (br * br + bi * bi);
+            kr += 0.5 * d.w * s * (br * ar + bi * ai);
+            ki += 0.5 * d.w * s * (br * ai - bi * ar);
+        }
+    }
+    double* base = d.dpart + slot * 3 * d.N;
+    stg(base + r, n);
+    stg(base + d.N + r, kr);
+    stg(base + 2 * d.N + r, ki);
 }
 
 // ---------------------------------------------------------------------------

@@ -273,7 +273,7 @@ struct KZFastArgs {
 template <typename T, int NZ, bool NT>
 __device__ __forceinline__ void kz_fast_body(const KZFastArgs<T>& a, const long long col) {
     __shared__ cpx<T> tab[NZ];
-    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = ld_hint<T, false>(a.tw + i);
     __syncthreads();
     if (col >= a.ncols) return;
     const long long jc = col / a.nxy, r = col - jc * a.nxy;
@@ -330,7 +330,7 @@ template <typename T, int NZ, int L, bool NT>
 __device__ __forceinline__ void kz_lanes_body(const KZFastArgs<T>& a, const long long t) {
     constexpr int P = NZ / L;
     __shared__ cpx<T> tab[NZ];
-    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = ld_hint<T, false>(a.tw + i);
     __syncthreads();
     const long long col = t / L;
     const int s = (int)(t % L);
@@ -398,7 +398,7 @@ template <typename T, int NZ>
 __global__ void __launch_bounds__(256) pz_kernel(const KZFastArgs<T> a, double* __restrict__ part) {
     __shared__ cpx<T> tab[NZ];
     __shared__ double red[256];
-    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = a.tw[i];
+    for (int i = threadIdx.x; i < NZ; i += blockDim.x) tab[i] = ld_hint<T, false>(a.tw + i);
     __syncthreads();
     const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
@@ -597,7 +597,7 @@ __device__ __forceinline__ void kp_fast_body(const KPArgs<T>& a, const cpx<T>* _
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
-    for (int i = tid; i < N; i += nth) tab[i] = twN[i];
+    for (int i = tid; i < N; i += nth) tab[i] = ld_hint<T, false>(twN + i);
     const int z = blockIdx.x;
     const bool act = tid < L * N;   // lanes of the row transforms
     cpx<T>* La = tab + N;
@@ -809,13 +809,13 @@ __device__ __forceinline__ void kp_fast_body(const KPArgs<T>& a, const cpx<T>* _
                 const int p = tid + i * NTH;
                 if (p >= NN) continue;
                 if (a.accumulate) {
-                    base[p] += dn[i];
-                    base[N3 + p] += dkr[i];
-                    base[2 * N3 + p] += dki[i];
+                    stg(base + p, ldg(base + p) + dn[i]);
+                    stg(base + N3 + p, ldg(base + N3 + p) + dkr[i]);
+                    stg(base + 2 * N3 + p, ldg(base + 2 * N3 + p) + dki[i]);
                 } else {
-                    base[p] = dn[i];
-                    base[N3 + p] = dkr[i];
-                    base[2 * N3 + p] = dki[i];
+                    stg(base + p, dn[i]);
+                    stg(base + N3 + p, dkr[i]);
+                    stg(base + 2 * N3 + p, dki[i]);
                 }
             }
         }
@@ -825,13 +825,13 @@ __device__ __forceinline__ void kp_fast_body(const KPArgs<T>& a, const cpx<T>* _
         for (int q = 0; q < P; ++q) {
             const int pt = row * N + s + L * q;
             if (a.accumulate) {
-                base[pt] += dn[q];
-                base[N3 + pt] += dkr[q];
-                base[2 * N3 + pt] += dki[q];
+                stg(base + pt, ldg(base + pt) + dn[q]);
+                stg(base + N3 + pt, ldg(base + N3 + pt) + dkr[q]);
+                stg(base + 2 * N3 + pt, ldg(base + 2 * N3 + pt) + dki[q]);
             } else {
-                base[pt] = dn[q];
-                base[N3 + pt] = dkr[q];
-                base[2 * N3 + pt] = dki[q];
+                stg(base + pt, dn[q]);
+                stg(base + N3 + pt, dkr[q]);
+                stg(base + 2 * N3 + pt, dki[q]);
             }
         }
     }
