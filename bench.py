@@ -152,14 +152,24 @@ def drift(obs0, obs1, steps):
             "N_rel_change": (obs1["N"] - obs0["N"]) / obs0["N"]}
 
 
+def in_kernel_z(prof):
+    """True when the ABM phases ran without z-axis launches: the plane kernel with the
+    z-term inside (kp_fast_zd) or the single-pass kernel."""
+    return prof["zaxis"][0] == 0 and prof["plane_abm1"][0] > 0
+
+
 def phase_roofline(prof, prof_steps, M, b_alg, rec=None):
     """Per-kernel bandwidth of the step.  The dominant kernel is the plane kernel of ABM
     phase 1; each ABM phase is charged half of the step's algorithmic bytes B_alg per
     qpwf (the unit the step fraction uses), and its design traffic (state arrays it
-    moves, including the z-term scratch) is given beside it."""
+    moves from HBM, including the z-term scratch where the z-axis kernel runs) is given
+    beside it."""
     out = {}
     arr = b_alg / 16.0                     # one state array of one qpwf
-    design = {"plane_abm1": 10, "plane_abm2": 6, "zaxis": 4}   # arrays per qpwf-step
+    if in_kernel_z(prof):
+        design = {"plane_abm1": 9, "plane_abm2": 5, "zaxis": 0}
+    else:
+        design = {"plane_abm1": 10, "plane_abm2": 6, "zaxis": 4}   # arrays per qpwf-step
     for name in ("plane_abm1", "plane_abm2", "zaxis"):
         n, ms = prof[name]
         if n == 0:
@@ -511,7 +521,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": dom["frac"],
                 "traffic": dom.get("pmc_traffic_per_launch"),
-                "kernel": "plane kernel of ABM phase 1 (kp_fast, mode KP_ABM1)",
+                "kernel": ("plane kernel of ABM phase 1 with the z-term inside (kp_fast_zd, mode KP_ABM1)"
+                           if in_kernel_z(prof) else "plane kernel of ABM phase 1 (kp_fast, mode KP_ABM1)"),
                 "launches": dom["launches"], "avg_launch_ms": dom["avg_launch_ms"],
                 "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
                 "alg_unit": "B_alg / 2 per qpwf of the launch (half of the step's 16 state arrays)",

@@ -153,7 +153,8 @@ typedef struct {
  *                the z kernel overlaps; default: about 1 GiB of qpwfs)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
  *                (sets the number of density partial sums; 0 = default:
- *                32, or 4 on the single-pass path below)
+ *                32, 16 on the single-pass path and 128 on the z_dense path
+ *                below)
  *   fused      : whole-cube kernel (one pass, the cube in LDS): 1 = whenever
  *                the cube fits in LDS; 0 = only where the register-FFT
  *                kernels below do not cover the lattice; -1 = never (always
@@ -186,7 +187,25 @@ typedef struct {
  *                (each lane nz/L points, exchanges across lanes); 0 =
  *                default (1); a value that does not divide nz into >= 2
  *                points per lane falls back to 1.  Errors: ARG for other
- *                values. */
+ *                values.
+ *   z_dense    : the ABM phases compute the z-term inside the plane kernel,
+ *                as the dense real symmetric nz x nz matrix T_z applied to
+ *                the z-columns of the input, instead of running the z-axis
+ *                kernel and reading its scratch back (no z-term scratch: 14
+ *                state arrays per step from HBM when the columns of a qpwf
+ *                stay in L2 while its planes are processed; one workgroup
+ *                takes 4 planes, the workgroups of one qpwf group are
+ *                launched onto one XCD, and one launch covers all qpwfs).
+ *                Available on cubic lattices of side 32 (float64 and
+ *                float32) and 16 (float64) on the register-FFT kernels, off
+ *                the single-pass path, without phase removal.  1 = on where
+ *                available, 0 = default (on for float64 side 32, where it
+ *                measured faster than the two kernels; float32 measured
+ *                slower), -1 = off.  jgroup's default is 128 on this path.
+ *                Results agree with the two-kernel path to rounding (dense
+ *                sums instead of transforms).  lise_autotune times both.
+ *                Errors: ARG for other values.  A context on this path is
+ *                stepped alone by lise_batch_step. */
 typedef struct {
     int32_t chunk_qpwf;
     int32_t jgroup;
@@ -196,6 +215,7 @@ typedef struct {
     int32_t graph;
     int32_t single_pass;
     int32_t z_lanes;
+    int32_t z_dense;
 } lise_tuning;
 
 /* Create a context for n_qpwf qpwfs on `lat` with functional `fn`, on the

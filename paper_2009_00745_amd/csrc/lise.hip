@@ -34,6 +34,7 @@ const char* kVersion = "lise-mi355x 0.1 (gfx950)";
 constexpr int kBatchPeriod = 4;   // ABM steps after which the buffer ring repeats
 constexpr int kPlaneJg = 32;      // default qpwfs per workgroup row of the plane kernels
 constexpr int kCubeJg = 16;       // ... of the single-pass kernel (one workgroup holds a whole qpwf)
+constexpr int kZdJg = 128;        // ... of the plane kernel with the z-term inside (measured 64-256 alike)
 constexpr size_t kDescRowsOffset = 1024;   // the one-entry table of a single system: descriptor, then rows
 
 // Staging memory of lise_apply_h_noalloc: one fixed array per GPU, held until
@@ -96,6 +97,7 @@ struct lise_ctx {
     size_t ah_cap = 0;
     void* scratch_dev = nullptr;  // this device's address of `scratch` (lise_apply_h_noalloc)
     void* cube_desc = nullptr;    // one-entry descriptor table of the single-pass kernel
+    void* tzm = nullptr;          // dense z-term operator T_z (nz x nz, the state's type)
     double* red = nullptr;     // reduction partials (observables)
     long long red_cap = 0;
     double* pz_part = nullptr;  // per-workgroup z-momentum sums (observables)
@@ -110,6 +112,8 @@ struct lise_ctx {
     int chunk = 0, jg = 32, fused_mode = 0, generic = 0;   // fused_mode: -1 never, 0 auto, 1 prefer
     int jg_user = 0;            // jgroup the caller set (0: the path's default)
     int single_pass = 0;        // -1 never, 0 auto, 1 prefer the single-pass ABM kernel
+    int z_dense_user = 0;       // -1 never, 0 default, 1 the in-kernel z-term where available
+    bool zdense = false;        // ABM phases: plane kernel with the z-term in the kernel
     int zl_user = 0;            // lanes per z-column the caller set (0: default)
     int zl = 1;                 // lanes per z-column of the register-FFT z kernel (1, 2 or 4)
     bool cube = false;          // ABM phases by the single-pass kernel (lise_cube.hpp)
@@ -260,6 +264,10 @@ void set_fast_attrs(int lim) {
     (void)hipFuncSetAttribute((const void*)kp_fast<T, NS, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute((const void*)kp_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if constexpr (zd_side((int)sizeof(T), NS)) {
+        (void)hipFuncSetAttribute((const void*)kp_fast_zd<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        (void)hipFuncSetAttribute((const void*)kp_fast_zd<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    }
     if constexpr (cube_side((int)sizeof(T), NS)) {
         (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         (void)hipFuncSetAttribute((const void*)kc_fast_batch<T, NS, KP_ABM2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -313,6 +321,46 @@ bool cube_eligible(const lise_ctx* c) {
            cube_lds_of((int)c->esz / 2, n) <= c->lds_limit && !c->remove_phase;
 }
 
+// The plane kernel with the z-term in the kernel (kp_fast_zd): cubic lattices
+// on the register-FFT kernels, the ABM phases without phase removal.
+bool zdense_eligible(const lise_ctx* c) {
+    const int n = c->lat.nx;
+    const int esz = (int)c->esz / 2;
+    const size_t lds = (size_t)(n + 2 * n * (n + 1)) * c->esz + (size_t)kZdPlanes * n * esz +
+                       (size_t)kZdPlanes * 3 * n * n * sizeof(double);
+    return c->fast_xy && c->fast_z && n == c->lat.ny && n == c->lat.nz && !c->remove_phase &&
+           (n == 16 || n == 32) && zd_side(esz, n) && lds <= c->lds_limit;
+}
+
+// T_z of Eq. (tdslda)'s kinetic term along z on the lattice: the z-axis
+// kernel multiplies the spectrum by c_z m^2 (m the signed index, Nyquist
+// kept) between a forward and an inverse transform of nz points, so
+// T_z[z][z'] = c_z sum_k m_k^2 cos(2 pi k (z - z') / nz) with
+// c_z = (2 pi^2 / L_z^2) / nz (the sine parts cancel: m_k^2 is even in k).
+// Summed in long double and rounded once to the state's type.
+template <typename T>
+int build_tzm(lise_ctx* c) {
+    const int nz = c->lat.nz;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double lz = (long double)nz * c->lat.a;
+    const long double cz = 2.0L * pi * pi / (lz * lz) / nz;
+    std::vector<long double> row(nz);
+    for (int d = 0; d < nz; ++d) {
+        long double sum = 0.0L;
+        for (int k = 0; k < nz; ++k) {
+            const long double m = (2 * k < nz) ? k : k - nz;
+            sum += m * m * cosl(2.0L * pi * (long double)((long long)k * d % nz) / nz);
+        }
+        row[d] = cz * sum;
+    }
+    std::vector<T> h((size_t)nz * nz);
+    for (int z = 0; z < nz; ++z)
+        for (int zp = 0; zp < nz; ++zp) h[(size_t)z * nz + zp] = T(row[(z - zp + nz) % nz]);
+    CHK(dalloc(c, &c->tzm, h.size() * sizeof(T)));
+    HIPCHK(c, hipMemcpy(c->tzm, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return LISE_OK;
+}
+
 // Choose launch geometry and (re)allocate scratch for the current tuning.
 int configure(lise_ctx* c) {
     c->config_version += 1;
@@ -350,7 +398,13 @@ int configure(lise_ctx* c) {
     // default where it measured faster than the two kernels
     c->cube = cube_eligible(c) &&
               (c->single_pass > 0 || (c->single_pass == 0 && cube_auto_of((int)c->esz / 2, nx)));
-    c->jg = c->jg_user > 0 ? c->jg_user : (c->cube ? kCubeJg : kPlaneJg);
+    // in-kernel z-term: by default where it measured faster than the two
+    // kernels (float64 side 32: 28.3 against 30.5 ms per step at 8192 qpwfs;
+    // float32 side 32 slower, 19.0 against 16.5)
+    c->zdense = !c->cube && zdense_eligible(c) &&
+                (c->z_dense_user > 0 || (c->z_dense_user == 0 && c->prec == LISE_FP64 && nx == 32));
+    c->jg = c->jg_user > 0 ? c->jg_user : (c->cube ? kCubeJg : (c->zdense ? kZdJg : kPlaneJg));
+    if (c->zdense && !c->tzm) CHK(c->prec == LISE_FP64 ? build_tzm<double>(c) : build_tzm<float>(c));
     static_assert(sizeof(KPArgs<double>) <= kDescRowsOffset, "descriptor table layout");
     if (c->cube && !c->cube_desc) CHK(dalloc(c, &c->cube_desc, kDescRowsOffset + 64));
     c->stream_hint = c->mfma_xy || (c->fast_xy && plane_stream_hint_of(c->esz / 2, nx));
@@ -480,6 +534,36 @@ void launch_kp_fast_n(lise_ctx* c, const KPArgs<T>& a, dim3 grid) {
     const size_t lds = std::max(kp_fast_lds<T, NS>(), (size_t)block * sizeof(double));
     hipLaunchKernelGGL((kp_fast<T, NS, MODE>), grid, dim3(block), lds, c->stream, a,
                        reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy);
+}
+
+template <typename T, int MODE, int NS>
+void launch_kp_zd_n(lise_ctx* c, const KPArgs<T>& a, int rows) {
+    if constexpr (zd_side((int)sizeof(T), NS)) {
+        constexpr int block = plane_block<T, NS>();
+        constexpr size_t lds = kpzd_lds<T, NS>();
+        hipLaunchKernelGGL((kp_fast_zd<T, NS, MODE>), dim3((unsigned)(NS / kZdPlanes * rows)), dim3(block), lds,
+                           c->stream, a, reinterpret_cast<const cpx<T>*>(c->tw) + c->tw_full_xy, rows);
+    }
+}
+
+// The ABM phases on the plane kernel with the z-term in the kernel: no
+// z-axis launch, no z-term scratch.
+template <typename T, int MODE>
+int launch_kpzd_t(lise_ctx* c, KPArgs<T> a, long long j0, int k, int cls) {
+    a.j0 = j0;
+    a.kcount = k;
+    a.G = nullptr;
+    a.tzm = reinterpret_cast<const T*>(c->tzm);
+    if (!a.tzm) return fail(c, LISE_E_STATE, "z-term operator table is not allocated");
+    const int rows = (k + a.jg - 1) / a.jg;
+    hipEvent_t ev;
+    prof_begin(c, cls, &ev);
+    switch (c->lat.nx) {
+        case 16: launch_kp_zd_n<T, MODE, 16>(c, a, rows); break;
+        default: launch_kp_zd_n<T, MODE, 32>(c, a, rows); break;
+    }
+    prof_end(c, cls, ev);
+    return check_launch(c, "kp_fast_zd");
 }
 
 template <int MODE, int NS>
@@ -750,6 +834,12 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
             }
             return LISE_OK;
         }
+        if (c->zdense && !a.eta) {
+            // plane kernel only, z-term in the kernel, all qpwfs in one launch
+            // (no scratch to size by chunks): ceil(count / jg) density slots
+            a.accumulate = 0;
+            return launch_kpzd_t<T, MODE>(c, a, first, (int)count, cls);
+        }
     }
     const bool ov = c->overlap && !c->fused && c->s2;
     if (ov) {
@@ -784,6 +874,13 @@ int apply_chunks(lise_ctx* c, KPArgs<T> a, long long first, long long count, int
 int slots_used(const lise_ctx* c, long long count) {
     const long long k = std::min<long long>(c->chunk, count);
     return (int)((k + c->jg - 1) / c->jg);
+}
+
+// density slots the ABM phases write: one launch over all qpwfs on the
+// in-kernel z-term path, else one chunk's workgroup rows (later chunks add
+// into the same slots)
+int abm_slots(const lise_ctx* c) {
+    return c->zdense ? (int)((c->M + c->jg - 1) / c->jg) : slots_used(c, c->M);
 }
 
 // Reduce density partials (nslots > 0) or reuse dens (nslots = 0), optional
@@ -921,7 +1018,7 @@ int abm_step_t(lise_ctx* c) {
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM1>(c, a, 0, c->M, 0, 1)));
     }
-    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, dt));
+    CHK(launch_fields(c, abm_slots(c), nullptr, c->dens_tmp, c->V_tmp, c->D_tmp, dt));
     // phase 2: H m -> m', y_{n+1}, p_{n+1} - c_{n+1}; densities of y_{n+1}
     {
         KPArgs<T> a = kp_base<T>(c);
@@ -935,7 +1032,7 @@ int abm_step_t(lise_ctx* c) {
         a.dens_src = 1;
         CHK((apply_chunks<T, KP_ABM2>(c, a, 0, c->M, 4, 1)));
     }
-    CHK(launch_fields(c, slots_used(c, c->M), nullptr, c->dens_cur, c->V_cur, c->D_cur, dt));
+    CHK(launch_fields(c, abm_slots(c), nullptr, c->dens_cur, c->V_cur, c->D_cur, dt));
     CHK(tick(c, dt));
     c->iy = ym1;
     c->dn = (c->dn + 1) % 4;
@@ -1560,7 +1657,7 @@ void bprof_end(lise_batch* b, int cls, hipEvent_t a, hipStream_t st) {
 // A system joins a group when both register-FFT kernels cover its lattice and
 // no per-qpwf pass (phase removal) or other plane kernel is in use.
 bool batch_groupable(const lise_ctx* c) {
-    return c->fast_xy && c->fast_z && !c->mfma_xy && !c->fused && !c->remove_phase && !c->generic;
+    return c->fast_xy && c->fast_z && !c->mfma_xy && !c->fused && !c->remove_phase && !c->generic && !c->zdense;
 }
 
 // slots and slot width of the separate density pass (as apply_chunks)
@@ -2378,12 +2475,14 @@ int lise_set_tuning(lise_ctx* c, const lise_tuning* t) {
     if (t->chunk_qpwf < 0 || t->jgroup < 0) return fail(c, LISE_E_ARG, "negative tuning value");
     if (t->z_lanes != 0 && t->z_lanes != 1 && t->z_lanes != 2 && t->z_lanes != 4)
         return fail(c, LISE_E_ARG, "z_lanes must be 0, 1, 2 or 4");
+    if (t->z_dense < -1 || t->z_dense > 1) return fail(c, LISE_E_ARG, "z_dense must be -1, 0 or 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->s2) HIPCHK(c, hipStreamSynchronize(c->s2));
     c->chunk = t->chunk_qpwf;
     c->jg_user = t->jgroup;
     c->single_pass = t->single_pass < 0 ? -1 : (t->single_pass > 0 ? 1 : 0);
     c->zl_user = t->z_lanes;
+    c->z_dense_user = t->z_dense;
     c->fused_mode = t->fused < 0 ? -1 : (t->fused > 0 ? 1 : 0);
     c->generic = t->generic ? 1 : 0;
     c->overlap = t->no_overlap ? 0 : 1;
@@ -2732,6 +2831,28 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
             t.no_overlap = 1;
             t.graph = c->use_graph;
             t.single_pass = 1;
+            t.z_dense = c->z_dense_user;
+            float ms = 0.0f;
+            rc = trial(t, trial_steps, &ms);
+            if (rc == LISE_OK) timed.push_back({ms, t});
+        }
+    }
+    // the plane kernel with the z-term inside (one launch per phase: no
+    // chunk or overlap to choose)
+    const bool zd_ok = c->z_dense_user >= 0 && zdense_eligible(c);
+    if (zd_ok) {
+        const int zjgs[] = {32, 64, 128, 256};
+        for (int jg : zjgs) {
+            if (rc != LISE_OK) break;
+            lise_tuning t{};
+            t.chunk_qpwf = (int32_t)std::min<long long>(c->M, gib);
+            t.jgroup = jg;
+            t.fused = c->fused_mode;
+            t.generic = c->generic;
+            t.no_overlap = 1;
+            t.graph = c->use_graph;
+            t.single_pass = -1;
+            t.z_dense = 1;
             float ms = 0.0f;
             rc = trial(t, trial_steps, &ms);
             if (rc == LISE_OK) timed.push_back({ms, t});
@@ -2749,6 +2870,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
                 t.no_overlap = nov;
                 t.graph = c->use_graph;
                 t.single_pass = cube_ok ? -1 : c->single_pass;
+                t.z_dense = zd_ok ? -1 : c->z_dense_user;
                 float ms = 0.0f;
                 rc = trial(t, trial_steps, &ms);
                 if (rc == LISE_OK) timed.push_back({ms, t});
@@ -2764,7 +2886,7 @@ int lise_autotune(lise_ctx* c, double dt, int32_t trial_steps, lise_tuning* chos
         for (size_t i = 0; i < std::min<size_t>(3, timed.size()); ++i) {
             lise_tuning t = timed[i].second;
             second.push_back(t);
-            if (t.single_pass > 0 || !c->fast_z) continue;
+            if (t.single_pass > 0 || t.z_dense > 0 || !c->fast_z) continue;
             for (int zl : {2, 4})
                 if (kz_lanes_valid(c->lat.nz, zl)) {
                     t.z_lanes = zl;
@@ -2855,6 +2977,7 @@ void lise_free(lise_ctx* c) {
     dfree(reinterpret_cast<void**>(&c->red));
     dfree(&c->ah_buf);
     dfree(&c->cube_desc);
+    dfree(&c->tzm);
     dfree(reinterpret_cast<void**>(&c->norms));
     dfree(reinterpret_cast<void**>(&c->norms0));
     dfree(reinterpret_cast<void**>(&c->eta));

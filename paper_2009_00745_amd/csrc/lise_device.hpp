@@ -341,6 +341,10 @@ struct KPArgs {
     // Parseval sums over the v components of (m_x, m_y) |F_xy v|^2 (signed
     // plane-wave indices, Nyquist index 0), for the total current
     double* ppart;
+    // ABM phases of the plane kernel with the z-term computed in the kernel:
+    // the kinetic operator along z as a dense real symmetric nz x nz matrix
+    // (row-major; null where the z-term comes from the z-axis kernel)
+    const T* tzm;
 };
 
 // ---------------------------------------------------------------------------

@@ -842,6 +842,239 @@ __global__ void __launch_bounds__((plane_block<T, N>()), LISE_KP_MIN_WAVES) kp_f
     kp_fast_body<T, N, MODE>(a, twN, (int)blockIdx.y);
 }
 
+// ---------------------------------------------------------------------------
+// The ABM phases with the z-term inside the plane kernel (z_dense).  The
+// kinetic operator along z is the real symmetric nz x nz matrix T_z (the z
+// kernel's transform, multiply, inverse transform written out), so the
+// z-term of a point is a dot product with its z-column.  One workgroup takes
+// kZdPlanes consecutive planes of its jg qpwfs: per qpwf and pair it reads
+// the z-columns at its points once and forms the z-terms of all its planes
+// in registers, then runs the xy transforms and the epilogue plane by plane.
+// The columns of a qpwf are read by nz / kZdPlanes workgroups; the launch
+// puts those on one XCD (xcd_plane_task) so that all but the first read hit
+// L2.  No z-axis kernel and no z-term scratch: 14 state arrays per ABM step
+// from HBM instead of 20.  Whole-line plane rows with at most two points per
+// lane (float64 sides 16, 32; float32 side 32).
+
+#ifndef LISE_ZD_PLANES
+#define LISE_ZD_PLANES 4
+#endif
+#ifndef LISE_ZD_UNROLL
+#define LISE_ZD_UNROLL 4
+#endif
+#ifndef LISE_ZD_XCD
+#define LISE_ZD_XCD 1
+#endif
+constexpr int kZdPlanes = LISE_ZD_PLANES;
+
+__host__ __device__ constexpr bool zd_side(int esz, int N) {
+    return N <= 32 && N % kZdPlanes == 0 && !plane_natural_of(esz, N) && N / plane_lanes_of(esz, N) <= 2;
+}
+
+// dynamic LDS: twiddles, the two padded row-transform planes, kZdPlanes rows
+// of T_z, and the float64 density sums of the workgroup's planes
+template <typename T, int N>
+constexpr size_t kpzd_lds() {
+    return (size_t)(N + 2 * N * (N + 1)) * sizeof(cpx<T>) + (size_t)kZdPlanes * N * sizeof(T) +
+           (size_t)kZdPlanes * 3 * N * N * sizeof(double);
+}
+
+// Workgroup b of a launch of nt x R tasks (nt plane tasks per row) -> (plane
+// task, row).  The dispatcher deals consecutive workgroups to the eight XCDs
+// in turn, so workgroup b runs on XCD b % 8; here the nt tasks of one row
+// (the same jg qpwfs, hence the same z-columns) are consecutive workgroups
+// of one XCD.  Rows beyond the last multiple of 8 map in plain order.  The
+// map is a bijection for any R, so results do not depend on where a
+// workgroup runs.
+__device__ __forceinline__ void xcd_plane_task(int b, int nt, int R, int& task, int& row) {
+    const int R8 = R & ~7;
+    const int head = nt * R8;
+    if (b < head) {
+        const int x = b & 7, o = b >> 3;
+        row = (o / nt) * 8 + x;
+        task = o % nt;
+    } else {
+        const int r = b - head;
+        row = R8 + r / nt;
+        task = r % nt;
+    }
+}
+
+template <typename T, int N, int MODE>
+__device__ __forceinline__ void kpzd_body(const KPArgs<T>& a, const cpx<T>* __restrict__ twN, const int by,
+                                          const int z0) {
+    static_assert(MODE == KP_ABM1 || MODE == KP_ABM2, "in-kernel z-term in the ABM phases only");
+    static_assert(zd_side((int)sizeof(T), N), "whole-line plane rows, at most two points per lane");
+    constexpr int PZ = kZdPlanes;
+    constexpr int L = plane_lanes<T, N>();
+    constexpr int P = N / L;
+    constexpr bool NT = plane_stream_hint<T, N>();
+    constexpr int LD = N + 1;
+    constexpr int NN = N * N;
+    constexpr long long nxy = NN;
+    constexpr long long N3 = nxy * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* La = tab + N;
+    cpx<T>* Lb = La + N * LD;
+    T* tzr = reinterpret_cast<T*>(Lb + N * LD);            // rows z0 .. z0 + PZ - 1 of T_z
+    double* Dl = reinterpret_cast<double*>(tzr + PZ * N);  // [PZ][3][NN] density sums
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (int i = tid; i < N; i += nth) tab[i] = ld_hint<T, false>(twN + i);
+    for (int i = tid; i < PZ * N; i += nth) tzr[i] = ldg(a.tzm + (long long)z0 * N + i);
+    if (a.dens_src)
+        for (int i = tid; i < PZ * 3 * NN; i += nth) Dl[i] = 0.0;
+    const int row = tid / L;
+    const int s = tid % L;
+    const int brs = bitrev(s, L);
+    const int jbeg = by * a.jg;
+    const int jend = min(a.kcount, jbeg + a.jg);
+    const T cdt = T(a.dt / 48.0);
+    const cpx<T> coef = mk(T(0), T(0));
+    double ekin = 0.0;
+    __syncthreads();
+    for (int jl = jbeg; jl < jend; ++jl) {
+        const long long jgl = a.j0 + jl;
+        for (int pr = 0; pr < a.npair; ++pr) {
+            const long long cola = (jgl * a.C + a.ca[pr]) * N3;
+            const long long colb = (jgl * a.C + a.cb[pr]) * N3;
+            // the z-terms of the PZ planes at this thread's points: one pass
+            // over the z-columns, summed in the order z' = 0, 1, ...
+            cpx<T> Ga[PZ][P], Gb[PZ][P];
+#pragma unroll
+            for (int pl = 0; pl < PZ; ++pl)
+#pragma unroll
+                for (int q = 0; q < P; ++q) Ga[pl][q] = Gb[pl][q] = mk(T(0), T(0));
+#pragma unroll LISE_ZD_UNROLL
+            for (int zz = 0; zz < N; ++zz) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int pt = row * N + s + L * q;
+                    const cpx<T> u = ld_hint<T, false>(a.in + cola + zz * nxy + pt);
+                    const cpx<T> v = ld_hint<T, false>(a.in + colb + zz * nxy + pt);
+#pragma unroll
+                    for (int pl = 0; pl < PZ; ++pl) {
+                        const T t = tzr[pl * N + zz];
+                        Ga[pl][q] = mk(Ga[pl][q].re + t * u.re, Ga[pl][q].im + t * u.im);
+                        Gb[pl][q] = mk(Gb[pl][q].re + t * v.re, Gb[pl][q].im + t * v.im);
+                    }
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < PZ; ++pl) {
+                const int z = z0 + pl;
+                const long long offa = cola + z * nxy, offb = colb + z * nxy;
+                cpx<T> xa[P], xb[P], fa[P], fb[P];
+                // the plane's own points (just read with the columns: cache hits)
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    fa[q] = ld_hint<T, false>(a.in + offa + row * N + s + L * q);
+                    fb[q] = ld_hint<T, false>(a.in + offb + row * N + s + L * q);
+                    xa[q] = fa[q];
+                    xb[q] = fb[q];
+                }
+                // rows: forward transform along x, transposed into LDS
+                lane_fwd<T, P, L>(xa, tab, s);
+                lane_fwd<T, P, L>(xb, tab, s);
+#pragma unroll
+                for (int k1 = 0; k1 < P; ++k1) {
+                    La[(k1 + P * brs) * LD + row] = xa[k1];
+                    Lb[(k1 + P * brs) * LD + row] = xb[k1];
+                }
+                __syncthreads();
+                {
+                    // columns (fixed kx): forward along y, multiply by
+                    // (c_x m_x^2 + c_y m_y^2), inverse along y
+                    const int col = row;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        xa[q] = La[col * LD + s + L * q];
+                        xb[q] = Lb[col * LD + s + L * q];
+                    }
+                    lane_fwd<T, P, L>(xa, tab, s);
+                    lane_fwd<T, P, L>(xb, tab, s);
+                    const int mx = (2 * col < N) ? col : col - N;
+                    const T fx = a.cx * T(mx * mx);
+#pragma unroll
+                    for (int k1 = 0; k1 < P; ++k1) {
+                        const int ky = k1 + P * brs;
+                        const int my = (2 * ky < N) ? ky : ky - N;
+                        const T f = fx + a.cy * T(my * my);
+                        xa[k1] = f * xa[k1];
+                        xb[k1] = f * xb[k1];
+                    }
+                    lane_inv<T, P, L>(xa, tab, s);
+                    lane_inv<T, P, L>(xb, tab, s);
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        La[col * LD + s + L * q] = xa[q];
+                        Lb[col * LD + s + L * q] = xb[q];
+                    }
+                }
+                __syncthreads();
+                // rows: inverse along x, then the epilogue at the thread's points
+#pragma unroll
+                for (int k1 = 0; k1 < P; ++k1) {
+                    xa[k1] = La[(k1 + P * brs) * LD + row];
+                    xb[k1] = Lb[(k1 + P * brs) * LD + row];
+                }
+                lane_inv<T, P, L>(xa, tab, s);
+                lane_inv<T, P, L>(xb, tab, s);
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int pt = row * N + s + L * q;
+                    double dn = 0.0, dkr = 0.0, dki = 0.0;
+                    point_epilogue<T, MODE, false, NT>(a, pr, xa[q] + Ga[pl][q], xb[q] + Gb[pl][q], fa[q], fb[q],
+                                                       offa + pt, offb + pt, (long long)z * nxy + pt, 0, 0, coef, cdt,
+                                                       T(0), dn, dkr, dki, ekin);
+                    if (a.dens_src) {
+                        double* d = Dl + pl * 3 * NN + pt;   // this thread's point only
+                        d[0] += dn;
+                        d[NN] += dkr;
+                        d[2 * NN] += dki;
+                    }
+                }
+                __syncthreads();   // La, Lb are rewritten by the next plane
+            }
+        }
+    }
+    if (a.dens_src) {
+#pragma unroll
+        for (int pl = 0; pl < PZ; ++pl) {
+            double* base = a.dpart + (long long)by * 3 * N3 + (long long)(z0 + pl) * nxy;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int pt = row * N + s + L * q;
+                const double* d = Dl + pl * 3 * NN + pt;
+                if (a.accumulate) {
+                    stg(base + pt, ldg(base + pt) + d[0]);
+                    stg(base + N3 + pt, ldg(base + N3 + pt) + d[NN]);
+                    stg(base + 2 * N3 + pt, ldg(base + 2 * N3 + pt) + d[2 * NN]);
+                } else {
+                    stg(base + pt, d[0]);
+                    stg(base + N3 + pt, d[NN]);
+                    stg(base + 2 * N3 + pt, d[2 * NN]);
+                }
+            }
+        }
+    }
+}
+
+// a one-dimensional grid of (N / kZdPlanes) plane tasks x R rows
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((plane_block<T, N>())) kp_fast_zd(const KPArgs<T> a, const cpx<T>* __restrict__ twN,
+                                                                   int R) {
+    int task, row;
+    if constexpr (LISE_ZD_XCD) {
+        xcd_plane_task((int)blockIdx.x, N / kZdPlanes, R, task, row);
+    } else {
+        row = (int)blockIdx.x / (N / kZdPlanes);
+        task = (int)blockIdx.x % (N / kZdPlanes);
+    }
+    kpzd_body<T, N, MODE>(a, twN, row, task * kZdPlanes);
+}
+
 // Systems of one lattice side advanced by one launch: tab[s] describes system
 // s (its buffers, fields, functional and qpwf count), rows[s] is the first
 // workgroup row of system s (rows[nsys] = gridDim.y).  Each workgroup finds

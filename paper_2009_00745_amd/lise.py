@@ -63,7 +63,8 @@ class Tuning(ct.Structure):
     _fields_ = [("chunk_qpwf", ct.c_int32), ("jgroup", ct.c_int32),
                 ("fused", ct.c_int32), ("generic", ct.c_int32),
                 ("no_overlap", ct.c_int32), ("graph", ct.c_int32),
-                ("single_pass", ct.c_int32), ("z_lanes", ct.c_int32)]
+                ("single_pass", ct.c_int32), ("z_lanes", ct.c_int32),
+                ("z_dense", ct.c_int32)]
 
 
 _lib = None
@@ -251,8 +252,8 @@ class Context:
         self._check(self.lib.lise_set_stream(self._h, ct.c_void_p(stream or 0)), "lise_set_stream")
 
     def set_tuning(self, chunk_qpwf=0, jgroup=0, fused=0, generic=0, no_overlap=0, graph=0, single_pass=0,
-                   z_lanes=0):
-        t = Tuning(chunk_qpwf, jgroup, fused, generic, no_overlap, graph, single_pass, z_lanes)
+                   z_lanes=0, z_dense=0):
+        t = Tuning(chunk_qpwf, jgroup, fused, generic, no_overlap, graph, single_pass, z_lanes, z_dense)
         self._check(self.lib.lise_set_tuning(self._h, ct.byref(t)), "lise_set_tuning")
 
     def profile(self, enable):

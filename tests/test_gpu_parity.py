@@ -748,8 +748,8 @@ def test_autotune_runs_and_keeps_invariants(lise):
     ctx = lise.Context(w.lattice, w.M, w.functional)
     ctx.set_qpwf(0, w.qpwfs())
     t = ctx.autotune(w.dt, 1)
-    assert t["jgroup"] in (2, 4, 8, 16, 32, 64) and t["chunk_qpwf"] >= 1
-    assert t["z_lanes"] in (0, 2, 4) and t["single_pass"] in (-1, 0, 1)
+    assert t["jgroup"] in (2, 4, 8, 16, 32, 64, 128, 256) and t["chunk_qpwf"] >= 1
+    assert t["z_lanes"] in (0, 2, 4) and t["single_pass"] in (-1, 0, 1) and t["z_dense"] in (-1, 0, 1)
     ctx.step(w.dt, 4)
     o = ctx.observables()
     assert o["norm_drift_max"] < 1e-10
