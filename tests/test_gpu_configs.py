@@ -60,13 +60,16 @@ def oracle_run(w, nsteps):
     return _ORACLE[key]
 
 
-def test_config2_lattice_fp64_100_steps_past_the_ramp(lise):
+@pytest.mark.parametrize("z_dense", [0, -1], ids=["default_in_kernel_z", "two_kernels"])
+def test_config2_lattice_fp64_100_steps_past_the_ramp(lise, z_dense):
     """32^3 config-2 recipe (lowest-|k| BCS, ramped Gaussian well), M = 16, 3 start-up +
     100 ABM steps (t = 103 dt, past the ramp's end at 100 dt): psi and densities within
-    1e-11 relative L2 of the oracle, observables within 1e-10."""
+    1e-11 relative L2 of the oracle, observables within 1e-10.  Both ABM paths: the
+    default (the z-term inside the plane kernel at this lattice) and the z-axis kernel
+    with the plane kernel."""
     w = wl.config2(M=16)
-    say(f"step {w.name} FP64 100 steps (chunk 6, 4 qpwfs per workgroup: ragged chunks and groups)")
-    g = gpu_run(lise, w, 100, tuning={"chunk_qpwf": 6, "jgroup": 4})
+    say(f"step {w.name} FP64 100 steps, z_dense {z_dense} (chunk 6, 4 qpwfs per workgroup: ragged chunks and groups)")
+    g = gpu_run(lise, w, 100, tuning={"chunk_qpwf": 6, "jgroup": 4, "z_dense": z_dense})
     ev = oracle_run(w, 100)
     n0, k0 = oracle.densities(ev.y, w.functional)
     e = (rel_l2(g["psi"], ev.y), rel_l2(g["dens"][0], n0), rel_l2(g["dens"][1], k0))
