@@ -759,7 +759,7 @@ int launch_kc_t(lise_ctx* c, KPArgs<T> a, long long j0, int k, int cls) {
         default: launch_kc_n<T, 20, MODE>(c, a, grid); break;
     }
     prof_end(c, cls, ev);
-    return check_launch(c, "kc_fast");
+    return check_launch(c, "kc_fast_batch");
 }
 
 // One Hamiltonian application over all qpwfs [first, first+count) in chunks:

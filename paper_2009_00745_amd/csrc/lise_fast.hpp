@@ -21,6 +21,11 @@
 //   (or, where L points of a row are less than a 128-byte line, through LDS
 //   in natural order: see kp_fast).
 //
+// ABM phases with the z-term inside the plane kernel (kp_fast_zd): the z
+//   kernel's transform pair is the dense real symmetric matrix T_z, applied
+//   to the z-columns of the input (read through L2) by the workgroups of
+//   the planes themselves, so the step needs no z-term scratch.
+//
 // pz_kernel: the z part of the total current by Parseval, for observables.
 #pragma once
 
