@@ -315,13 +315,14 @@ int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *tot
 
 /* Timed search over launch tuning for this system: chunk size, qpwfs per
  * plane workgroup 8/16/32/64 and z-kernel overlap on the two-kernel path,
- * and 2/4/8/16 qpwfs per workgroup on the single-pass path where it applies;
- * each candidate runs one untimed and `trial_steps` timed ABM steps with
- * step size dt on the live state (the state advances; results change only
- * in rounding).  The three fastest run again over 2 * trial_steps, each also
- * with 2 and 4 lanes per z-column where the z kernel runs, and the fastest
- * of that round is kept and written to *chosen (may be NULL).  Runs the start-up first if needed.
- * Errors: ARG, STATE, HIP, NAN. */
+ * 2/4/8/16 qpwfs per workgroup on the single-pass path and 32/64/128/256 on
+ * the in-kernel z-term path where those apply (not where the tuning turned
+ * them off); each candidate runs one untimed and `trial_steps` timed ABM
+ * steps with step size dt on the live state (the state advances; results
+ * change only in rounding).  The three fastest run again over
+ * 2 * trial_steps, each two-kernel one also with 2 and 4 lanes per z-column,
+ * and the fastest of that round is kept and written to *chosen (may be
+ * NULL).  Runs the start-up first if needed.  Errors: ARG, STATE, HIP, NAN. */
 int lise_autotune(lise_ctx *c, double dt, int32_t trial_steps, lise_tuning *chosen);
 
 /* Checkpoint and restart (Sec. "Checkpoint and restart").
