@@ -562,6 +562,15 @@ def main():
     if w.functional.ext_A != 0.0:
         drift_main["note"] = ("the external well is ramped on over the first 100 steps of the run: E changes "
                               "by the work of the time-dependent field, not by integration error alone")
+        # after the timed region: the same state stepped on past the end of the ramp, then E
+        # over 20 steps of a static Hamiltonian, where its change is integration error alone
+        past = int(np.ceil(w.functional.ext_t_on / w.dt)) + 1 - int(round(t_now / w.dt))
+        if past > 0:
+            ctx.step(w.dt, past)
+        oa = ctx.observables()
+        ctx.step(w.dt, 20)
+        ob = ctx.observables()
+        drift_main["after_ramp"] = dict(drift(oa, ob, 20), steps=20, t_start=float(oa["t"]))
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
