@@ -584,8 +584,10 @@ def read_checkpoint(path):
 
 def test_checkpoint_with_history_continues_bitwise(lise, tmp_path):
     """save(with_history) + load + step equals uninterrupted stepping bit for bit (FP64 with
-    overlap and graph replays, FP32), and the saved ABM history matches the oracle's."""
-    cases = [(wl.config2(M=24, n=16), {"graph": 1}), (wl.config3(M=16, n=20, precision=wl.FP32), {})]
+    overlap and graph replays, FP32, FP64 32^3 on the in-kernel z-term path), and the saved
+    ABM history matches the oracle's."""
+    cases = [(wl.config2(M=24, n=16), {"graph": 1}), (wl.config3(M=16, n=20, precision=wl.FP32), {}),
+             (wl.config2(M=6, n=32), {"z_dense": 1, "jgroup": 2})]
     for w, tuning in cases:
         path = str(tmp_path / f"{w.name}.ckpt")
         say(f"checkpoint {w.name}: 7 steps, save, 9 more; reload and 9 steps")

@@ -56,11 +56,13 @@ def cfg2(M, n, p):
 #   32^3 float64: 9 rows of one qpwf = 8 rows on the XCD map + 1 in plain order
 #   16^3 float64, C = 4: two pairs; 20 rows (16 mapped + 4), two chunks
 #   32^3 float32: 3 rows, two chunks
+#   32^3 float64, one qpwf, default tuning (128 qpwfs per row): a single row
 CASES = [
     ("32c_fp64", lambda p: cfg2(9, 32, p), {"jgroup": 1}, 1e-11),
     ("16c_fp64_c4", lambda p: wl.config4(M=40, n=16, precision=p), {"jgroup": 2, "chunk_qpwf": 24,
                                                                      "single_pass": -1}, 1e-11),
     ("32c_fp32", lambda p: cfg2(6, 32, p), {"jgroup": 2, "chunk_qpwf": 4}, 1e-5),
+    ("32c_fp64_m1", lambda p: cfg2(1, 32, p), {}, 1e-11),     # one qpwf: one row, in plain order
 ]
 
 
