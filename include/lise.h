@@ -150,7 +150,7 @@ typedef struct {
 /* Launch tuning (0 = library default).
  *   chunk_qpwf : qpwfs per launch of the two apply-H kernels; sizes the
  *                z-term scratch (chunk x C x N elements, a second one when
- *                the z kernel overlaps; default: about 1 GiB of qpwfs)
+ *                the z kernel overlaps; default: about 4 GiB of qpwfs)
  *   jgroup     : qpwfs that one workgroup of the plane kernel walks through
  *                (sets the number of density partial sums; 0 = default:
  *                32, 16 on the single-pass path and 128 on the z_dense path
@@ -313,11 +313,12 @@ int lise_set_tuning(lise_ctx *c, const lise_tuning *t);
 int lise_profile(lise_ctx *c, int32_t enable);
 int lise_profile_read(lise_ctx *c, int32_t which, int64_t *launches, double *total_ms);
 
-/* Timed search over launch tuning for this system: chunk size, qpwfs per
- * plane workgroup 8/16/32/64 and z-kernel overlap on the two-kernel path,
- * 2/4/8/16 qpwfs per workgroup on the single-pass path and 32/64/128/256 on
- * the in-kernel z-term path where those apply (not where the tuning turned
- * them off); each candidate runs one untimed and `trial_steps` timed ABM
+/* Timed search over launch tuning for this system: chunk size (1/4, 1, 2 and
+ * 4 GiB of qpwfs), qpwfs per plane workgroup 8/16/32/64 and z-kernel overlap
+ * on the two-kernel path, 2/4/8/16 qpwfs per workgroup on the single-pass
+ * path and 32/64/128/256 on the in-kernel z-term path where those apply (not
+ * where the tuning turned them off); each candidate runs one untimed and
+ * `trial_steps` timed ABM
  * steps with step size dt on the live state (the state advances; results
  * change only in rounding).  The three fastest run again over
  * 2 * trial_steps, each two-kernel one also with 2 and 4 lanes per z-column,
