@@ -43,9 +43,10 @@ def oracle_densities_chunked(w, piece=512):
 
 def test_config2_full_size(lise):
     w = wl.config2()
-    say(f"full size {w.name}: upload (launch shape of the benchmark's autotuned runs)")
+    say(f"full size {w.name}: upload (launch shape of the benchmark's autotuned runs: the z-term "
+        f"inside the plane kernel, 256 qpwfs per workgroup row)")
     ctx = lise.Context(w.lattice, w.M, w.functional)
-    ctx.set_tuning(chunk_qpwf=2048, jgroup=8, no_overlap=1)
+    ctx.set_tuning(jgroup=256, no_overlap=1, z_dense=1)
     upload(ctx, w)
     n, k = ctx.densities()
     n0, k0 = oracle_densities_chunked(w)
@@ -89,12 +90,13 @@ def test_config2_full_size(lise):
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         say(f"  evolved apply_h qpwf {j}: rel max err {err:.2e}")
         assert err < 1e-12
-    # and the GPU step must agree with a second GPU run in a different launch shape
+    # and the GPU step must agree with a second GPU run on the other ABM path (z-axis
+    # kernel + plane kernel, overlapped, ragged chunks)
     psi = ctx.get_qpwf(0, 64)
     ctx.close()
-    say("  same evolution with another chunking")
+    say("  same evolution on the two-kernel path with another chunking")
     ctx2 = lise.Context(w.lattice, w.M, w.functional)
-    ctx2.set_tuning(chunk_qpwf=3000, jgroup=32, no_overlap=0)
+    ctx2.set_tuning(chunk_qpwf=3000, jgroup=32, no_overlap=0, z_dense=-1)
     upload(ctx2, w)
     ctx2.step(w.dt, 6)
     psi2 = ctx2.get_qpwf(0, 64)
