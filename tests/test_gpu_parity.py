@@ -773,14 +773,18 @@ def test_deterministic_repeats(lise):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-def test_time_reversal(lise):
-    w = wl.config1(M=128)
+@pytest.mark.parametrize("case", ["8c_single_pass", "32c_in_kernel_z"])
+def test_time_reversal(lise, case):
+    """40 ABM steps forward and 40 back (dt -> -dt) return to the initial qpwfs: the 8^3
+    single-pass path and the 32^3 FP64 default path (z-term inside the plane kernel;
+    the external well's ramp depends on t only, so the backward run retraces it)."""
+    w, dt = (wl.config1(M=128), 0.004) if case == "8c_single_pass" else (wl.config2(M=8), 0.002)
     psi = w.qpwfs()
-    say("time reversal 8^3 M=128: 40 forward, 40 backward")
+    say(f"time reversal {w.name}: 40 forward, 40 backward, dt {dt}")
     ctx = lise.Context(w.lattice, w.M, w.functional)
     ctx.set_qpwf(0, psi)
-    ctx.step(0.004, 40)
-    ctx.step(-0.004, 40)
+    ctx.step(dt, 40)
+    ctx.step(-dt, 40)
     got = ctx.get_qpwf(0, w.M)
     t, _ = ctx.time()
     ctx.close()

@@ -203,7 +203,7 @@ def config1(seed=0, M=None):
     M = 1024 if M is None else M
     copies = 2 if M % 2 == 0 else 1
     gen = uniform_bcs(lat, fn, M, 0.5, 1.0, copies=copies, eps=1e-3, seed=seed)
-    return Workload("cfg1_fp64_8c_m1024", lat, fn, M, 0.005, 100, gen, seed,
+    return Workload(f"cfg1_fp64_8c_m{M}", lat, fn, M, 0.005, 100, gen, seed,
                     "8^3 uniform BCS, both spin blocks explicit (w=1), 1e-3 noise")
 
 
