@@ -229,9 +229,9 @@ def run_cfg3(steps, warmup, err_M, err_steps):
     plus its float32 density error against float64 on a reduced instance."""
     import torch
     w = make_workload("cfg3")
-    ctx, el, prof = run_gpu(w, steps, warmup, None, autotune=False)
+    ctx, el, prof = run_gpu(w, steps, warmup, None, autotune=True)
     ps = prof.pop("steps")
-    prof.pop("tuning")
+    chosen = prof.pop("tuning")
     obs0 = prof.pop("obs0")
     obs1 = ctx.observables()
     mem = ctx.memory()
@@ -249,6 +249,7 @@ def run_cfg3(steps, warmup, err_M, err_steps):
            "step_hbm_frac": value * b_alg / HBM_PEAK, "b_alg_per_qpwf_step": b_alg,
            "kernels": phase_roofline(prof, ps, w.M, b_alg, rec),
            "kernel_ms_per_step": {k: ms / ps for k, (n, ms) in prof.items()},
+           "tuning": chosen,
            "drift": drift(obs0, obs1, steps)}
     if err_M:
         out["density_error_vs_fp64"] = reduced_error("cfg3", err_steps, err_M)
